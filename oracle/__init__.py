@@ -1,0 +1,262 @@
+"""Plain FP64 CPU oracle for the Ehrenfests'-step-regularised lattice
+Boltzmann method (Brownlee, Gorban, Levesley 2007) and for the learned warm
+start of its entropic quasiequilibrium solve.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` import this package.  It shares no code with
+the GPU library ``paper_0705_4371_amd``; the arithmetic lives in
+``oracle.c`` (plain C, FP64, long double for Delta S), this module only
+marshals numpy arrays.
+
+Every function names the passage of the paper it follows in ``oracle.c``.
+Functions without an independent pin are listed as "parity unpinned" in the
+design notes; every function here has at least one pin in
+``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+QE_POLY, QE_ENTROPIC_MM, QE_ENTROPIC_M = 0, 1, 2
+BC_PERIODIC, BC_ZEROGRAD, BC_FREESLIP, BC_INLET_EQ = 0, 1, 2, 3
+COLL_LBGK, COLL_ELBM = 0, 1
+MLP_NPARAM = 4740
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc into liboracle.so (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+             "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(C.Structure):
+    _fields_ = [
+        ("Q", C.c_int32), ("qe", C.c_int32), ("collision", C.c_int32), ("pad0", C.c_int32),
+        ("nx", C.c_int64), ("ny", C.c_int64),
+        ("nu", C.c_double), ("delta", C.c_double), ("k", C.c_int64),
+        ("bc", C.c_int32 * 4),
+        ("inlet_rho", C.c_double), ("inlet_u1", C.c_double), ("inlet_u2", C.c_double),
+        ("solid_x0", C.c_int64), ("solid_y0", C.c_int64), ("solid_w", C.c_int64), ("solid_h", C.c_int64),
+    ]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n_above", C.c_int64), ("n_selected", C.c_int64), ("n_invalid", C.c_int64),
+                ("n_fallback", C.c_int64), ("sums", C.c_double * 4)]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+_I32 = C.POINTER(C.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        L.or_velocities.argtypes = [C.c_int, _I32, _I32, _D]
+        L.or_moments.argtypes = [C.c_int, _D, _D]
+        L.or_qe_poly.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _D]
+        L.or_qe_entropic_mm.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _D]
+        L.or_fstar_feasible.argtypes = [_D]
+        L.or_fstar_newton.argtypes = [_D, C.c_double, C.c_int, _D, _D]
+        L.or_fstar_scalar.argtypes = [_D, _D]
+        L.or_fstar_from_mu.argtypes = [_D, _D]
+        L.or_delta_S.argtypes = [C.c_int, _D, _D]
+        L.or_delta_S.restype = C.c_longdouble
+        L.or_elbm_alpha.argtypes = [C.c_int, _D, _D]
+        L.or_elbm_alpha.restype = C.c_double
+        L.or_init.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _D]
+        L.or_step.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _I64, C.POINTER(_Info)]
+        L.or_mlp_forward.argtypes = [_D, _D, C.c_int64, _D, C.c_int]
+        L.or_mlp_forward.restype = C.c_double
+        L.or_mlp_loss_grad.argtypes = [_D, _D, _D, C.c_int64, _D, C.c_int]
+        L.or_mlp_loss_grad.restype = C.c_double
+        L.or_adam_step.argtypes = [_D, _D, _D, _D, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                   C.c_double, C.c_double]
+        L.or_bf16_round.argtypes = [C.c_double]
+        L.or_bf16_round.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def velocities(Q: int):
+    vx = np.zeros(Q, np.int32)
+    vy = np.zeros(Q, np.int32)
+    w = np.zeros(Q, np.float64)
+    rc = lib().or_velocities(Q, vx.ctypes.data_as(_I32), vy.ctypes.data_as(_I32), _p(w))
+    if rc != 0:
+        raise ValueError("Q must be 3 or 9")
+    return vx, vy, w
+
+
+def moments(Q: int, f) -> np.ndarray:
+    f = np.ascontiguousarray(f, np.float64)
+    M = np.zeros(4)
+    lib().or_moments(Q, _p(f), _p(M))
+    return M
+
+
+def qe_poly(Q: int, rho: float, u1: float, u2: float = 0.0) -> np.ndarray:
+    out = np.zeros(Q)
+    lib().or_qe_poly(Q, rho, u1, u2, _p(out))
+    return out
+
+
+def qe_entropic_mm(Q: int, rho: float, u1: float, u2: float = 0.0) -> np.ndarray:
+    out = np.zeros(Q)
+    lib().or_qe_entropic_mm(Q, rho, u1, u2, _p(out))
+    return out
+
+
+def fstar_feasible(M) -> bool:
+    M = np.ascontiguousarray(M, np.float64)
+    return bool(lib().or_fstar_feasible(_p(M)))
+
+
+def fstar_newton(M, tol: float = 1e-13, max_iter: int = 100):
+    """f*_M multipliers by damped Newton.  Returns (mu, iterations, residual);
+    iterations < 0 flags an infeasible (-1) or unconverged (-2) site."""
+    M = np.ascontiguousarray(M, np.float64)
+    mu = np.zeros(4)
+    r = np.zeros(1)
+    it = lib().or_fstar_newton(_p(M), tol, max_iter, _p(mu), _p(r))
+    return mu, int(it), float(r[0])
+
+
+def fstar_scalar(M):
+    """f*_M multipliers through the product structure and bisection on ln Z."""
+    M = np.ascontiguousarray(M, np.float64)
+    mu = np.zeros(4)
+    rc = lib().or_fstar_scalar(_p(M), _p(mu))
+    return (mu if rc == 0 else None)
+
+
+def fstar_from_mu(mu) -> np.ndarray:
+    mu = np.ascontiguousarray(mu, np.float64)
+    out = np.zeros(9)
+    lib().or_fstar_from_mu(_p(mu), _p(out))
+    return out
+
+
+def delta_S(f, fs) -> float:
+    f = np.ascontiguousarray(f, np.float64)
+    fs = np.ascontiguousarray(fs, np.float64)
+    return float(lib().or_delta_S(len(f), _p(f), _p(fs)))
+
+
+def elbm_alpha(f, fs) -> float:
+    f = np.ascontiguousarray(f, np.float64)
+    fs = np.ascontiguousarray(fs, np.float64)
+    return float(lib().or_elbm_alpha(len(f), _p(f), _p(fs)))
+
+
+def make_cfg(Q=9, qe=QE_POLY, nx=16, ny=1, nu=1e-3, delta=float("inf"), k=0,
+             bc=(BC_PERIODIC,) * 4, inlet_rho=1.0, inlet_u=(0.0, 0.0), solid=(0, 0, 0, 0),
+             collision=COLL_LBGK) -> _Cfg:
+    c = _Cfg()
+    c.Q, c.qe, c.collision = Q, qe, collision
+    c.nx, c.ny = nx, ny
+    c.nu, c.delta, c.k = nu, delta, k
+    for i in range(4):
+        c.bc[i] = bc[i]
+    c.inlet_rho, c.inlet_u1, c.inlet_u2 = inlet_rho, inlet_u[0], inlet_u[1]
+    c.solid_x0, c.solid_y0, c.solid_w, c.solid_h = solid
+    return c
+
+
+def cfg_from_dict(d: dict) -> _Cfg:
+    return make_cfg(**d)
+
+
+def init(cfg: _Cfg, rho0, u0, twoE0=None) -> np.ndarray:
+    """f(x, 0) = quasiequilibrium of (rho0, u0[, 2E0]); arrays [ny][nx], u0 [2][ny][nx]."""
+    N = cfg.nx * cfg.ny
+    rho0 = np.ascontiguousarray(rho0, np.float64).reshape(-1)
+    u0 = np.ascontiguousarray(u0, np.float64).reshape(-1)
+    assert rho0.size == N and u0.size in (N, 2 * N)
+    if u0.size == N:
+        u0 = np.concatenate([u0, np.zeros(N)])
+    f = np.zeros((cfg.Q, cfg.ny, cfg.nx))
+    e = None
+    if twoE0 is not None:
+        e = np.ascontiguousarray(twoE0, np.float64).reshape(-1)
+    lib().or_init(C.byref(cfg), _p(rho0), _p(u0), _p(e) if e is not None else None, _p(f))
+    return f
+
+
+def step(cfg: _Cfg, f_in: np.ndarray) -> dict:
+    """One time step (pre-collision f(t) -> pre-collision f(t+1)).  Returns
+    dict(f, dS, sel, n_above, n_selected, n_invalid, n_fallback, sums)."""
+    f_in = np.ascontiguousarray(f_in, np.float64)
+    assert f_in.shape == (cfg.Q, cfg.ny, cfg.nx)
+    f_out = np.zeros_like(f_in)
+    dS = np.zeros((cfg.ny, cfg.nx))
+    sel = np.zeros(max(int(cfg.k), 1), np.int64)
+    info = _Info()
+    rc = lib().or_step(C.byref(cfg), _p(f_in), _p(f_out), _p(dS), sel.ctypes.data_as(_I64),
+                       C.byref(info))
+    if rc != 0:
+        raise MemoryError("oracle step failed (%d)" % rc)
+    return dict(f=f_out, dS=dS, sel=sel[:info.n_selected].copy(), n_above=info.n_above,
+                n_selected=info.n_selected, n_invalid=info.n_invalid,
+                n_fallback=info.n_fallback, sums=np.array(info.sums[:]))
+
+
+def run(cfg: _Cfg, f: np.ndarray, nsteps: int) -> np.ndarray:
+    for _ in range(nsteps):
+        f = step(cfg, f)["f"]
+    return f
+
+
+# ---------------------------------------------------------------------------
+# MLP 4 -> 64 -> 64 -> 4 (SiLU)
+# ---------------------------------------------------------------------------
+
+def bf16_round(x: float) -> float:
+    return float(lib().or_bf16_round(float(x)))
+
+
+def mlp_forward(params, x, bf16: bool = False) -> np.ndarray:
+    p = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[0]
+    y = np.zeros((n, 4))
+    lib().or_mlp_forward(_p(p), _p(x), n, _p(y), int(bf16))
+    return y
+
+
+def mlp_loss_grad(params, x, t, bf16: bool = False):
+    p = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().or_mlp_loss_grad(_p(p), _p(x), _p(t), x.shape[0], _p(g), int(bf16))
+    return float(loss), g
+
+
+def adam_step(p, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays p, m, v."""
+    lib().or_adam_step(_p(p), _p(m), _p(v), _p(np.ascontiguousarray(g, np.float64)), p.size, t,
+                       lr, b1, b2, eps)
