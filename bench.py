@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Throughput of the Ehrenfests'-regularised LBGK time step on one MI355X.
+
+Workload (default): the doubly periodic D2Q9 double shear layer,
+8192 x 4096 sites, FP32 populations, polynomial quasiequilibrium,
+nu = 1e-6, delta = 1e-4, k = 4096 -- the HBM-bound configuration whose
+throughput is reported in MLUPS and against the HBM roofline.  A "step" is
+one full time step: fused stream/collide with Delta S screening, FP64
+ranking of the screened sites, top-k selection and the Ehrenfests' reset.
+
+Prints one JSON line:
+  value      MLUPS (fluid sites x steps / s) over the timed steps
+  roofline   the fused step kernel (k_step): algorithmic bytes per launch
+             (72 B per site in FP32, 144 B in FP64: every population read
+             once and written once) / its mean launch duration measured
+             with HIP events on the context's stream during the timed steps
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp"):
+        with open(os.path.join(ROOT, "paper_0705_4371_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: str, prec: str, n_sites: int):
+    """HBM bytes per k_step launch from the committed rocprofv3 PMC summary,
+    or None if the summary is missing or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "k_step_%s_%s_pmc.json" % (workload, prec))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(args):
+    """The oracle (single thread, FP64 C) on a row band of the same shear
+    layer: nx x rows sites, `steps` steps, periodic."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    d, rho, u = W.shear_layer(nx=args.cpu_nx, ny=args.cpu_rows, width=80.0 * args.cpu_rows / 4096)
+    cfg = oracle.cfg_from_dict(d)
+    f = oracle.init(cfg, rho, u)
+    t0 = time.perf_counter()
+    for _ in range(args.cpu_steps):
+        f = oracle.step(cfg, f)["f"]
+    dt = time.perf_counter() - t0
+    n = args.cpu_nx * args.cpu_rows
+    return {"value": n * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "%d x %d band of the shear layer (same nu, delta, k), %d steps, FP64, %.1f s"
+                      % (args.cpu_nx, args.cpu_rows, args.cpu_steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--nx", type=int, default=8192)
+    ap.add_argument("--ny", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-nx", type=int, default=8192)
+    ap.add_argument("--cpu-rows", type=int, default=512)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the lattice would be split into y-slabs with halo exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0705_4371_amd.lbm as lbm
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    prec = lbm.LBM_FP64 if args.precision == "fp64" else lbm.LBM_FP32
+    d, rho, u = W.shear_layer(nx=args.nx, ny=args.ny)
+    workload = "shear_%dx%d" % (args.nx, args.ny)
+    print("# workload %s %s: building fields" % (workload, args.precision), file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        cfg = lbm.config_from_workload(d, prec, stream=stream.cuda_stream)
+        lat = lbm.Lattice(cfg, rho, u)
+    del rho, u
+    n_sites = args.nx * args.ny
+
+    print("# warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    lat.set_timing(True)
+    print("# timed %d steps" % args.steps, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_n = lat.kernel_time()
+    lat.set_timing(False)
+    st, _, _ = lat.stats()
+    ms_per_step = dt * 1e3 / args.steps
+    mlups = n_sites * args.steps / dt / 1e6
+
+    bytes_per_site = 72 if prec == lbm.LBM_FP32 else 144
+    k_avg_s = k_ms / 1e3 / max(k_n, 1)
+    achieved = bytes_per_site * n_sites / k_avg_s / 1e9
+    traffic = traffic_from_profile(workload, args.precision, n_sites)
+
+    out = {
+        "metric": "MLUPS + %HBM roofline; MLP-warm vs plain Newton f*_M at <=1e-10 residual",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == lbm.LBM_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 double shear layer %dx%d periodic, polynomial QE, nu=1e-6, "
+                               "delta=1e-4, k=4096" % (args.nx, args.ny),
+                   "sites": n_sites, "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step", "kernel_ms": round(k_avg_s * 1e3, 4),
+                     "bytes_per_site": bytes_per_site},
+        "ehrenfest": {"n_above_delta_last": st.n_above_delta, "selected_total": st.total_selected,
+                      "mass": st.mass},
+    }
+    lat.close()
+    if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for lattice Boltzmann
+ * steps regularised by Ehrenfests' steps (Brownlee, Gorban, Levesley,
+ * "Stable simulation of fluid flow with high-Reynolds number using
+ * Ehrenfests' steps", 2007), and for the entropic quasiequilibrium f*_M
+ * with its learned (MLP) Newton warm start.
+ *
+ * Conventions for every entry point:
+ *  - Return value: LBM_OK (0) or a negative LBM_E_* code.  No exception,
+ *    abort or exit crosses this boundary.  lbm_last_error() returns a
+ *    thread-local message for the last failure.
+ *  - Arguments are validated on the host before any HIP call, so invalid
+ *    arguments yield LBM_E_INVAL even on a machine without a GPU.
+ *  - Array arguments marked "device" are device pointers owned by the
+ *    caller; they must stay valid until the work queued on the context's
+ *    stream has completed.  Arguments marked "host" are host memory.
+ *  - Population arrays have the layout f[i][y][x] (x fastest, no padding)
+ *    with the paper's numbering: D1Q3 (rest, left, right) from Sec. 4.1;
+ *    D2Q9 (rest, E, N, W, S, NE, NW, SW, SE) from Sec. 4.2.  Their element
+ *    type is float for LBM_FP32 contexts and double for LBM_FP64 contexts.
+ *  - Site index s = x + nx * y.
+ *  - A context is bound to one HIP stream and is not thread-safe.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_E_INVAL = -1,     /* invalid argument or configuration            */
+  LBM_E_NOMEM = -2,     /* device allocation failed                     */
+  LBM_E_DEVICE = -3,    /* a HIP call failed (no device, launch error)  */
+  LBM_E_NONFINITE = -4, /* non-finite populations were detected         */
+  LBM_E_NOCONV = -5,    /* f*_M solve left sites above the tolerance    */
+  LBM_E_STATE = -6      /* call not valid in the context's state        */
+};
+
+enum { LBM_D1Q3 = 3, LBM_D2Q9 = 9 };
+/* quasiequilibrium: polynomial (Sec. 4.1 / cited D2Q9 form), entropic with
+   mass and momentum (closed forms of Sec. 4.1 and Sec. 4.2), entropic with
+   mass, momentum and energy f*_M (Sec. 2 argmax with M = (rho, rho u, 2E)) */
+enum { LBM_QE_POLY = 0, LBM_QE_ENTROPIC_MM = 1, LBM_QE_ENTROPIC_M = 2 };
+enum { LBM_FP32 = 0, LBM_FP64 = 1 };
+/* boundary rules; west/east accept PERIODIC, ZEROGRAD, INLET_EQ;
+   south/north accept PERIODIC, ZEROGRAD, FREESLIP */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_ZEROGRAD = 1, LBM_BC_FREESLIP = 2, LBM_BC_INLET_EQ = 3 };
+/* collision: LBGK (eq. lbgkLB) or ELBM (eq. elbmLB) */
+enum { LBM_COLL_LBGK = 0, LBM_COLL_ELBM = 1 };
+/* f*_M Newton start */
+enum { LBM_START_DEFAULT = 0, LBM_START_CLOSED_FORM = 1, LBM_START_MLP = 2 };
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; owns all device memory it allocates */
+typedef struct lbm_mlp lbm_mlp; /* opaque; owns weights and optimiser state    */
+
+typedef struct lbm_config {
+  int32_t lattice;    /* LBM_D1Q3 or LBM_D2Q9                                   */
+  int32_t qe;         /* LBM_QE_*                                               */
+  int32_t precision;  /* LBM_FP32 or LBM_FP64: storage and collision arithmetic */
+  int32_t collision;  /* LBM_COLL_*                                             */
+  int64_t nx, ny;     /* lattice size; D1Q3 requires ny == 1; nx >= 2, ny >= 1  */
+  double nu;          /* kinematic viscosity > 0; beta = 1/(1 + 6 nu)           */
+  double delta;       /* Ehrenfests' tolerance on Delta S, >= 0 (+inf: off)     */
+  int32_t k;          /* at most k Ehrenfests' steps per time step, >= 0        */
+  int32_t fstar_start;/* LBM_START_* (LBM_QE_ENTROPIC_M only)                   */
+  int32_t bc[4];      /* west, east, south, north                               */
+  double inlet_rho;   /* inlet state for LBM_BC_INLET_EQ                        */
+  double inlet_u[2];
+  int64_t solid_x0, solid_y0, solid_w, solid_h; /* solid square (w == 0: none)  */
+  const lbm_mlp* net; /* warm-start network for LBM_START_MLP, else NULL        */
+  void* stream;       /* hipStream_t used for all work of the context (0: null) */
+} lbm_config;
+
+typedef struct lbm_es_stats {
+  int64_t step;          /* time steps taken since init / set_populations          */
+  int64_t n_above_delta; /* last step: sites with Delta S > delta                  */
+  int64_t n_selected;    /* last step: sites returned to quasiequilibrium          */
+  int64_t n_invalid;     /* last step: sites with Delta S = +inf (f < 0 or f* <= 0) */
+  int64_t n_fallback;    /* last step: f*_M sites that used the fallback            */
+  int64_t total_selected;/* all steps since init                                   */
+  int64_t nonfinite;     /* sticky: non-finite post-collision values were written  */
+  int64_t pad0;
+  double kth_dS;         /* last step: smallest selected Delta S (0 if none)       */
+  double max_dS;         /* last step: largest Delta S above delta (0 if none)     */
+  double mass, mom[2], energy; /* last step: FP64 sums over fluid sites of rho,
+                                  rho u1, rho u2, 2E of the pre-collision state   */
+} lbm_es_stats;
+
+/* Fills *cfg with defaults: D2Q9, polynomial QE, FP32, LBGK, 64 x 64
+   periodic, nu = 1e-3, delta = +inf, k = 0. */
+void lbm_config_default(lbm_config* cfg);
+
+/* Host-only validation of a configuration (no HIP call). */
+int lbm_validate_config(const lbm_config* cfg);
+
+/*
+ * Creates a context and sets f(x, 0) to the configured quasiequilibrium of
+ * the initial fields (Sec. 4.1 / Sec. 4.2 initial states).
+ *   rho0  device double [ny][nx]
+ *   u0    device double [2][ny][nx] (D1Q3: [1][ny][nx])
+ *   twoE0 device double [ny][nx], 2E/rho, required for LBM_QE_ENTROPIC_M,
+ *         else NULL
+ * Solid sites hold zero populations.  *out receives the context.
+ */
+int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const double* twoE0,
+             lbm_ctx** out);
+
+/*
+ * Advances nsteps >= 0 time steps of eq. (ESLB) (LBGK with Ehrenfests'
+ * steps; Sec. 3.2 "return to quasiequilibrium" for the selected sites):
+ * per step, at every fluid site the moments, f* and
+ * Delta S = sum_i f_i ln(f_i / f*_i) - f_i + f*_i (Sec. 3.3, +inf if some
+ * f_i < 0 or f*_i <= 0) are computed; the sites with Delta S > delta are
+ * ranked (largest first, ties by lower site index); at most k of them are
+ * set to f*, all other fluid sites take f + 2 beta (f* - f); then free
+ * flight with the boundary rules.  Queued asynchronously on the context's
+ * stream; returns LBM_E_NONFINITE without queuing work once a previous
+ * lbm_ehrenfest_stats call has reported non-finite values.
+ */
+int lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/*
+ * Moments of the current pre-collision state f(x, t), FP64, into device
+ * double arrays [ny][nx] (any pointer may be NULL): rho, rho u1, rho u2
+ * (u is [2][ny][nx]: rho u1 then rho u2), 2E (Sec. 2, M = (rho, rho u1,
+ * rho u2, 2E)).  Solid sites give zeros.
+ */
+int lbm_moments(lbm_ctx* ctx, double* rho, double* rhou, double* twoE);
+
+/* Current pre-collision populations f(x, t) into a device array of the
+   context's precision [Q][ny][nx]; zeros at solid sites. */
+int lbm_get_populations(lbm_ctx* ctx, void* f);
+
+/* Replaces the state by the pre-collision populations f(x, t) given in a
+   device array [Q][ny][nx]; resets the sticky non-finite flag and the step
+   counter; returns LBM_E_NONFINITE if f holds a non-finite value. */
+int lbm_set_populations(lbm_ctx* ctx, const void* f);
+
+/*
+ * Synchronises the context's stream and reports the last step's
+ * Ehrenfests' statistics (host *out).  sel (host, may be NULL) receives up
+ * to sel_cap selected site indices in rank order (Delta S descending, site
+ * ascending), sel_dS (host, may be NULL) their FP64 Delta S.
+ */
+int lbm_ehrenfest_stats(lbm_ctx* ctx, lbm_es_stats* out, int64_t* sel, double* sel_dS,
+                        int64_t sel_cap);
+
+/*
+ * Synchronises and copies the last step's candidate list -- every fluid
+ * site with FP64 Delta S > delta, in no particular order -- into host
+ * arrays sites / dS of capacity cap; *n receives the full count.
+ */
+int lbm_candidates(lbm_ctx* ctx, int64_t* sites, double* dS, int64_t cap, int64_t* n);
+
+/*
+ * Kernel timing for measurement: with on != 0, lbm_step launches the step
+ * kernels directly (no graph replay) and brackets each fused step kernel
+ * with HIP events on the context's stream; lbm_kernel_time synchronises and
+ * returns the summed duration in ms and the number of timed launches of
+ * that kernel since timing was switched on.
+ */
+int lbm_set_timing(lbm_ctx* ctx, int on);
+int lbm_kernel_time(lbm_ctx* ctx, double* ms, int64_t* launches);
+
+/* Lattice geometry actually allocated: row pitch in elements (>= nx, a
+   multiple of 64) and bytes of one population buffer. */
+int lbm_layout(const lbm_ctx* ctx, int64_t* pitch, int64_t* buffer_bytes);
+
+/* sizeof(lbm_config) and sizeof(lbm_es_stats) as compiled into the
+   library, so that bindings can check their struct layouts (host only). */
+void lbm_struct_sizes(int64_t* config_size, int64_t* stats_size);
+
+void lbm_free(lbm_ctx* ctx);
+const char* lbm_strerror(int code);
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,520 @@
+// lbm_api.hip -- C ABI (include/lbm.h) over the gfx950 step kernels.
+//
+// Host-side responsibilities: argument validation before any HIP call,
+// device buffers (two population buffers plus the Ehrenfests' ranking
+// scratch), the buffer swap, hipGraph capture of runs of steps, optional HIP
+// event timing of the fused step kernel, and the statistics read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_launch.hpp"
+
+using namespace lbm;
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(LBM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// graph replays cover this many steps (even, so the state returns to its buffer)
+static constexpr int GRAPH_STEPS = 32;
+
+struct lbm_ctx {
+  lbm_config cfg;
+  StepArgs args;        // template; A/B set per launch
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;          // buffer holding the state
+  bool canonical = true;
+  int64_t step = 0;
+  bool nonfinite_seen = false;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  double time_ms = 0.0;
+  int64_t launches = 0;
+  int64_t N = 0, pitch = 0, plane = 0;
+  size_t elem = 4;
+  // scratch
+  uint32_t* ctr = nullptr;
+  uint32_t* screen = nullptr;
+  Cand* cand = nullptr;
+  Cand* bnd = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* sel = nullptr;
+  double* sel_ds = nullptr;
+  DevStats* st = nullptr;
+  double* partials = nullptr;
+};
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err; }
+
+const char* lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_E_INVAL: return "invalid argument";
+    case LBM_E_NOMEM: return "device allocation failed";
+    case LBM_E_DEVICE: return "HIP device error";
+    case LBM_E_NONFINITE: return "non-finite populations";
+    case LBM_E_NOCONV: return "f*_M solve did not converge";
+    case LBM_E_STATE: return "invalid state for this call";
+    default: return "unknown error";
+  }
+}
+
+void lbm_config_default(lbm_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->lattice = LBM_D2Q9;
+  c->qe = LBM_QE_POLY;
+  c->precision = LBM_FP32;
+  c->collision = LBM_COLL_LBGK;
+  c->nx = 64;
+  c->ny = 64;
+  c->nu = 1e-3;
+  c->delta = INFINITY;
+  c->k = 0;
+  c->fstar_start = LBM_START_DEFAULT;
+  for (int i = 0; i < 4; ++i) c->bc[i] = LBM_BC_PERIODIC;
+  c->inlet_rho = 1.0;
+}
+
+int lbm_validate_config(const lbm_config* c) {
+  if (!c) return fail(LBM_E_INVAL, "config is NULL");
+  if (c->lattice != LBM_D1Q3 && c->lattice != LBM_D2Q9)
+    return fail(LBM_E_INVAL, "lattice must be LBM_D1Q3 (3) or LBM_D2Q9 (9), got %d", c->lattice);
+  if (c->qe != LBM_QE_POLY && c->qe != LBM_QE_ENTROPIC_MM && c->qe != LBM_QE_ENTROPIC_M)
+    return fail(LBM_E_INVAL, "qe must be one of LBM_QE_*, got %d", c->qe);
+  if (c->qe == LBM_QE_ENTROPIC_M)
+    return fail(LBM_E_INVAL, "LBM_QE_ENTROPIC_M time stepping is not available in this library build");
+  if (c->precision != LBM_FP32 && c->precision != LBM_FP64)
+    return fail(LBM_E_INVAL, "precision must be LBM_FP32 or LBM_FP64, got %d", c->precision);
+  if (c->collision != LBM_COLL_LBGK)
+    return fail(LBM_E_INVAL, "only LBM_COLL_LBGK is available in this library build");
+  if (c->nx < 2 || c->ny < 1) return fail(LBM_E_INVAL, "need nx >= 2 and ny >= 1 (got %lld x %lld)",
+                                         (long long)c->nx, (long long)c->ny);
+  if (c->lattice == LBM_D1Q3 && c->ny != 1) return fail(LBM_E_INVAL, "D1Q3 requires ny == 1");
+  if (c->nx > (int64_t)1 << 31 || c->ny > (int64_t)1 << 31 || c->nx * c->ny >= (int64_t)0xFFFFFFFFll)
+    return fail(LBM_E_INVAL, "lattice too large: nx * ny must be below 2^32 - 1");
+  if (!(c->nu >= 0.0)) return fail(LBM_E_INVAL, "nu must be >= 0 (got %g)", c->nu);
+  if (!(c->delta >= 0.0)) return fail(LBM_E_INVAL, "delta must be >= 0 or +inf (got %g)", c->delta);
+  if (c->k < 0) return fail(LBM_E_INVAL, "k must be >= 0 (got %d)", c->k);
+  if (c->k > 0 && (int64_t)c->k > c->nx * c->ny) return fail(LBM_E_INVAL, "k exceeds the number of sites");
+  for (int s = 0; s < 4; ++s) {
+    const int b = c->bc[s];
+    const bool ok = s < 2 ? (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_INLET_EQ)
+                          : (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_FREESLIP);
+    if (!ok) return fail(LBM_E_INVAL, "boundary rule %d not allowed on side %d", b, s);
+  }
+  if ((c->bc[0] == LBM_BC_PERIODIC) != (c->bc[1] == LBM_BC_PERIODIC))
+    return fail(LBM_E_INVAL, "west and east must both be periodic or both not");
+  if ((c->bc[2] == LBM_BC_PERIODIC) != (c->bc[3] == LBM_BC_PERIODIC))
+    return fail(LBM_E_INVAL, "south and north must both be periodic or both not");
+  if (c->bc[2] != LBM_BC_PERIODIC && c->ny < 2)
+    return fail(LBM_E_INVAL, "non-periodic south/north rules need ny >= 2");
+  if (c->lattice == LBM_D1Q3 && c->bc[2] != LBM_BC_PERIODIC)
+    return fail(LBM_E_INVAL, "D1Q3 has no y direction: south/north must be LBM_BC_PERIODIC");
+  if ((c->bc[0] == LBM_BC_INLET_EQ || c->bc[1] == LBM_BC_INLET_EQ)) {
+    if (!(c->inlet_rho > 0.0) || !std::isfinite(c->inlet_u[0]) || !std::isfinite(c->inlet_u[1]))
+      return fail(LBM_E_INVAL, "inlet state must have rho > 0 and finite velocity");
+    if (c->qe == LBM_QE_ENTROPIC_MM && (std::fabs(c->inlet_u[0]) >= 1.0 || std::fabs(c->inlet_u[1]) >= 1.0))
+      return fail(LBM_E_INVAL, "entropic inlet state needs |u_j| < 1");
+  }
+  if (c->solid_w < 0 || c->solid_h < 0) return fail(LBM_E_INVAL, "solid size must be >= 0");
+  if (c->solid_w > 0 && c->solid_h > 0) {
+    if (c->lattice == LBM_D1Q3) return fail(LBM_E_INVAL, "solid obstacles need D2Q9");
+    if (c->solid_x0 < 0 || c->solid_y0 < 0 || c->solid_x0 + c->solid_w > c->nx ||
+        c->solid_y0 + c->solid_h > c->ny)
+      return fail(LBM_E_INVAL, "solid square must lie inside the lattice");
+  }
+  return LBM_OK;
+}
+
+static void qe_host(int Q, int qe, double rho, double ux, double uy, double* fs) {
+  if (qe == LBM_QE_POLY) {
+    if (Q == 3) {
+      fs[0] = (2.0 * rho / 3.0) * (1.0 - 1.5 * ux * ux);
+      fs[1] = (rho / 6.0) * (1.0 - 3.0 * ux + 3.0 * ux * ux);
+      fs[2] = (rho / 6.0) * (1.0 + 3.0 * ux + 3.0 * ux * ux);
+    } else {
+      static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+      const double uu = ux * ux + uy * uy;
+      for (int i = 0; i < 9; ++i) {
+        const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        const double cu = cx[i] * ux + cy[i] * uy;
+        fs[i] = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      }
+    }
+  } else {
+    const double sx = std::sqrt(1.0 + 3.0 * ux * ux), X = (2.0 * ux + sx) / (1.0 - ux);
+    if (Q == 3) {
+      fs[0] = rho * (2.0 - sx) * (2.0 / 3.0);
+      fs[1] = rho * (2.0 - sx) / 6.0 / X;
+      fs[2] = rho * (2.0 - sx) / 6.0 * X;
+    } else {
+      static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+      const double sy = std::sqrt(1.0 + 3.0 * uy * uy), Y = (2.0 * uy + sy) / (1.0 - uy);
+      for (int i = 0; i < 9; ++i) {
+        const double w = i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        fs[i] = rho * w * (2.0 - sx) * (2.0 - sy) * std::pow(X, cx[i]) * std::pow(Y, cy[i]);
+      }
+    }
+  }
+}
+
+static void ctx_release(lbm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (int p = 0; p < 2; ++p) {
+    if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
+    if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+  }
+  for (auto& e : c->ev_used) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& e : c->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  void* ptrs[] = {c->buf[0], c->buf[1], c->ctr, c->screen, c->cand, c->bnd, c->hist, c->sel, c->sel_ds,
+                  c->st, c->partials};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
+
+static StepArgs args_for(const lbm_ctx* c, int src, int dst) {
+  StepArgs a = c->args;
+  a.A = c->buf[src];
+  a.B = c->buf[dst];
+  return a;
+}
+
+int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const double* twoE0,
+             lbm_ctx** out) {
+  if (!out) return fail(LBM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int rc = lbm_validate_config(cfg);
+  if (rc) return rc;
+  if (!rho0 || !u0) return fail(LBM_E_INVAL, "rho0 and u0 are required");
+  if (cfg->qe == LBM_QE_ENTROPIC_M && !twoE0) return fail(LBM_E_INVAL, "twoE0 is required for f*_M");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(LBM_E_DEVICE, "no HIP device");
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_E_NOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  const int Q = cfg->lattice;
+  c->elem = cfg->precision == LBM_FP64 ? 8 : 4;
+  c->N = cfg->nx * cfg->ny;
+  c->pitch = (cfg->nx + 63) / 64 * 64;
+  c->plane = c->pitch * cfg->ny;
+  c->stream = (hipStream_t)cfg->stream;
+
+  StepArgs& a = c->args;
+  std::memset(&a, 0, sizeof(a));
+  Geom& g = a.g;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.pitch = c->pitch;
+  g.plane = c->plane;
+  for (int s = 0; s < 4; ++s) g.bc[s] = cfg->bc[s];
+  if (cfg->solid_w > 0 && cfg->solid_h > 0) {
+    g.sx0 = cfg->solid_x0;
+    g.sy0 = cfg->solid_y0;
+    g.sx1 = cfg->solid_x0 + cfg->solid_w;
+    g.sy1 = cfg->solid_y0 + cfg->solid_h;
+  } else {
+    g.sx0 = g.sx1 = g.sy0 = g.sy1 = -4;
+  }
+  double feq[9] = {0};
+  if (cfg->bc[0] == LBM_BC_INLET_EQ || cfg->bc[1] == LBM_BC_INLET_EQ)
+    qe_host(Q, cfg->qe, cfg->inlet_rho, cfg->inlet_u[0], Q == 9 ? cfg->inlet_u[1] : 0.0, feq);
+  for (int i = 0; i < 9; ++i) g.feq_in[i] = feq[i];
+  g.beta2 = 2.0 / (1.0 + 6.0 * cfg->nu);
+  g.delta = cfg->delta;
+  g.ds_on = std::isinf(cfg->delta) ? 0 : 1;
+  g.kmax = cfg->k;
+  // FP32 screen threshold delta (1 - 1e-2) - 64 eps32 sqrt(delta rho)
+  const double dclamp = std::min(cfg->delta, 3.0e38);
+  a.thr_a = (float)(0.99 * dclamp);
+  a.thr_b = (float)(64.0 * std::ldexp(1.0, -24) * std::sqrt(dclamp));
+  a.ntx = (cfg->nx + STEP_TX - 1) / STEP_TX;
+  a.nblocks = a.ntx * cfg->ny;
+  a.prec = cfg->precision;
+  a.Q = Q;
+  a.qe = cfg->qe;
+
+  const size_t bytes = (size_t)Q * (size_t)c->plane * c->elem;
+  const size_t ncap = (size_t)c->N;
+  const size_t kcap = (size_t)std::max(cfg->k, 1);
+#define ALLOC(ptr, nbytes)                                                              \
+  do {                                                                                \
+    if (hipMalloc((void**)&(ptr), (nbytes)) != hipSuccess) {                          \
+      ctx_release(c);                                                                 \
+      return fail(LBM_E_NOMEM, "hipMalloc of %zu bytes failed", (size_t)(nbytes));    \
+    }                                                                                 \
+  } while (0)
+  ALLOC(c->buf[0], bytes);
+  ALLOC(c->buf[1], bytes);
+  ALLOC(c->ctr, sizeof(uint32_t) * C_COUNT);
+  ALLOC(c->screen, sizeof(uint32_t) * ncap);
+  ALLOC(c->cand, sizeof(Cand) * ncap);
+  ALLOC(c->bnd, sizeof(Cand) * ncap);
+  ALLOC(c->hist, sizeof(uint32_t) * HIST_BINS);
+  ALLOC(c->sel, sizeof(uint32_t) * kcap);
+  ALLOC(c->sel_ds, sizeof(double) * kcap);
+  ALLOC(c->st, sizeof(DevStats));
+  ALLOC(c->partials, sizeof(double) * 4 * (size_t)a.nblocks);
+#undef ALLOC
+  a.ctr = c->ctr;
+  a.screen = c->screen;
+  a.cand = c->cand;
+  a.bnd = c->bnd;
+  a.hist = c->hist;
+  a.sel = c->sel;
+  a.sel_ds = c->sel_ds;
+  a.st = c->st;
+  a.partials = c->partials;
+
+  hipError_t e = launch_clear(args_for(c, 0, 0), c->stream);
+  if (e == hipSuccess) e = launch_init(args_for(c, 1, 0), rho0, u0, twoE0, c->stream);
+  if (e != hipSuccess) {
+    ctx_release(c);
+    return fail(LBM_E_DEVICE, "init kernels: %s", hipGetErrorString(e));
+  }
+  c->cur = 0;
+  c->canonical = true;
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_free(lbm_ctx* ctx) { ctx_release(ctx); }
+
+void lbm_struct_sizes(int64_t* config_size, int64_t* stats_size) {
+  if (config_size) *config_size = (int64_t)sizeof(lbm_config);
+  if (stats_size) *stats_size = (int64_t)sizeof(lbm_es_stats);
+}
+
+static int ensure_graph(lbm_ctx* c, int from) {
+  if (c->gexec[from]) return LBM_OK;
+  if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  int s = from;
+  hipError_t err = hipSuccess;
+  for (int t = 0; t < GRAPH_STEPS && err == hipSuccess; ++t) {
+    err = launch_step(args_for(c, s, 1 - s), true, c->cap, nullptr, nullptr);
+    s = 1 - s;
+  }
+  hipGraph_t gr = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap, &gr);
+  if (err != hipSuccess || e2 != hipSuccess) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return fail(LBM_E_DEVICE, "graph capture: %s", hipGetErrorString(err != hipSuccess ? err : e2));
+  }
+  c->graph[from] = gr;
+  HIPCHK(hipGraphInstantiate(&c->gexec[from], gr, nullptr, nullptr, 0));
+  return LBM_OK;
+}
+
+static int timed_launch(lbm_ctx* c, bool pull) {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!c->ev_free.empty()) {
+    ev = c->ev_free.back();
+    c->ev_free.pop_back();
+  } else {
+    HIPCHK(hipEventCreate(&ev.first));
+    HIPCHK(hipEventCreate(&ev.second));
+  }
+  c->ev_used.push_back(ev);
+  HIPCHK(launch_step(args_for(c, c->cur, 1 - c->cur), pull, c->stream, ev.first, ev.second));
+  return LBM_OK;
+}
+
+static int drain_events(lbm_ctx* c) {
+  if (c->ev_used.empty()) return LBM_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (auto& e : c->ev_used) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+    c->time_ms += ms;
+    c->launches++;
+    c->ev_free.push_back(e);
+  }
+  c->ev_used.clear();
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_E_INVAL, "nsteps must be >= 0");
+  if (c->nonfinite_seen) return fail(LBM_E_NONFINITE, "non-finite populations were reported; set new populations");
+  int rc;
+  while (n > 0) {
+    if (c->canonical || c->timing) {
+      const bool pull = !c->canonical;
+      if (c->timing) {
+        if ((rc = timed_launch(c, pull))) return rc;
+        if (c->ev_used.size() >= 1024 && (rc = drain_events(c))) return rc;
+      } else {
+        HIPCHK(launch_step(args_for(c, c->cur, 1 - c->cur), pull, c->stream, nullptr, nullptr));
+      }
+      c->cur = 1 - c->cur;
+      c->canonical = false;
+      c->step++;
+      n--;
+      continue;
+    }
+    if (n >= GRAPH_STEPS) {
+      if ((rc = ensure_graph(c, c->cur))) return rc;
+      HIPCHK(hipGraphLaunch(c->gexec[c->cur], c->stream));
+      c->step += GRAPH_STEPS;
+      n -= GRAPH_STEPS;
+      continue;
+    }
+    HIPCHK(launch_step(args_for(c, c->cur, 1 - c->cur), true, c->stream, nullptr, nullptr));
+    c->cur = 1 - c->cur;
+    c->step++;
+    n--;
+  }
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx* c, void* f) {
+  if (!c || !f) return fail(LBM_E_INVAL, "ctx and f are required");
+  HIPCHK(launch_get(args_for(c, c->cur, c->cur), !c->canonical, f, c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* c, const void* f) {
+  if (!c || !f) return fail(LBM_E_INVAL, "ctx and f are required");
+  HIPCHK(launch_clear(args_for(c, c->cur, c->cur), c->stream));
+  HIPCHK(launch_set(args_for(c, c->cur, c->cur), f, c->stream));
+  uint32_t flags[C_COUNT];
+  HIPCHK(hipMemcpyAsync(flags, c->ctr, sizeof(flags), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->canonical = true;
+  c->step = 0;
+  c->nonfinite_seen = false;
+  if (flags[C_NONFINITE + 2]) {
+    c->nonfinite_seen = true;
+    return fail(LBM_E_NONFINITE, "populations hold non-finite values");
+  }
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* rhou, double* e2) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  HIPCHK(launch_moments(args_for(c, c->cur, c->cur), !c->canonical, rho, rhou, e2, c->stream));
+  return LBM_OK;
+}
+
+int lbm_ehrenfest_stats(lbm_ctx* c, lbm_es_stats* out, int64_t* sel, double* sel_dS, int64_t cap) {
+  if (!c || !out) return fail(LBM_E_INVAL, "ctx and out are required");
+  if (cap < 0) return fail(LBM_E_INVAL, "sel_cap must be >= 0");
+  HIPCHK(launch_finalize(c->args, c->stream));
+  DevStats st;
+  uint32_t ctr[C_COUNT];
+  HIPCHK(hipMemcpyAsync(&st, c->st, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::memset(out, 0, sizeof(*out));
+  out->step = c->step;
+  out->n_above_delta = (int64_t)st.n_above;
+  out->n_selected = (int64_t)st.n_sel;
+  out->n_invalid = (int64_t)st.n_invalid;
+  out->n_fallback = 0;
+  out->total_selected = (int64_t)st.total_sel;
+  out->nonfinite = ctr[C_NONFINITE] ? 1 : 0;
+  out->kth_dS = st.kth;
+  out->max_dS = st.max;
+  out->mass = st.sums[0];
+  out->mom[0] = st.sums[1];
+  out->mom[1] = st.sums[2];
+  out->energy = st.sums[3];
+  if (out->nonfinite) c->nonfinite_seen = true;
+  if ((sel || sel_dS) && st.n_sel > 0 && cap > 0) {
+    std::vector<uint32_t> s(st.n_sel);
+    std::vector<double> d(st.n_sel);
+    HIPCHK(hipMemcpy(s.data(), c->sel, sizeof(uint32_t) * st.n_sel, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(d.data(), c->sel_ds, sizeof(double) * st.n_sel, hipMemcpyDeviceToHost));
+    std::vector<size_t> order(st.n_sel);
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+      if (d[x] != d[y]) return d[x] > d[y];
+      return s[x] < s[y];
+    });
+    const int64_t m = std::min<int64_t>(cap, (int64_t)st.n_sel);
+    for (int64_t i = 0; i < m; ++i) {
+      if (sel) sel[i] = s[order[i]];
+      if (sel_dS) sel_dS[i] = d[order[i]];
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_candidates(lbm_ctx* c, int64_t* sites, double* dS, int64_t cap, int64_t* n) {
+  if (!c || !n) return fail(LBM_E_INVAL, "ctx and n are required");
+  if (cap < 0) return fail(LBM_E_INVAL, "cap must be >= 0");
+  DevStats st;
+  HIPCHK(hipMemcpyAsync(&st, c->st, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *n = (int64_t)st.n_above;
+  const int64_t m = std::min<int64_t>(cap, *n);
+  if (m > 0) {
+    std::vector<Cand> v((size_t)m);
+    HIPCHK(hipMemcpy(v.data(), c->cand, sizeof(Cand) * (size_t)m, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) {
+      if (sites) sites[i] = v[(size_t)i].site;
+      if (dS) dS[i] = v[(size_t)i].ds;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_set_timing(lbm_ctx* c, int on) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  int rc = drain_events(c);
+  if (rc) return rc;
+  c->timing = on != 0;
+  c->time_ms = 0.0;
+  c->launches = 0;
+  return LBM_OK;
+}
+
+int lbm_kernel_time(lbm_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return fail(LBM_E_INVAL, "ctx, ms and launches are required");
+  int rc = drain_events(c);
+  if (rc) return rc;
+  *ms = c->time_ms;
+  *launches = c->launches;
+  return LBM_OK;
+}
+
+int lbm_layout(const lbm_ctx* c, int64_t* pitch, int64_t* bytes) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (pitch) *pitch = c->pitch;
+  if (bytes) *bytes = (int64_t)c->cfg.lattice * c->plane * (int64_t)c->elem;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+// lbm_device.hpp -- device-side lattice tables and per-site arithmetic of the
+// Ehrenfests'-step regularised LBGK step (gfx950).
+//
+// Velocity numbering follows the paper: D1Q3 (rest, left, right), Sec. 4.1;
+// D2Q9 (rest, E, N, W, S, NE, NW, SW, SE), Sec. 4.2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Lattice tables
+// ---------------------------------------------------------------------------
+template <int Q> struct Lat;
+
+template <> struct Lat<9> {
+  static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  // opposite velocity (bounce-back) and vertical mirror (free-slip)
+  static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  static constexpr int mir[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+  // weights 4/9, 1/9, 1/36 (Sec. 4.2)
+  static __host__ __device__ constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+template <> struct Lat<3> {
+  static constexpr int cx[3] = {0, -1, 1};
+  static constexpr int cy[3] = {0, 0, 0};
+  static constexpr int opp[3] = {0, 2, 1};
+  static constexpr int mir[3] = {0, 1, 2};
+  // weights 2/3, 1/6, 1/6 (Sec. 4.1)
+  static __host__ __device__ constexpr double w(int i) { return i == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+};
+
+enum : int { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_FREESLIP = 2, BC_INLET_EQ = 3 };
+enum : int { QE_POLY = 0, QE_ENTROPIC_MM = 1, QE_ENTROPIC_M = 2 };
+
+// Geometry and per-step parameters passed by value to every step kernel.
+struct Geom {
+  int64_t nx, ny, pitch, plane;  // plane = pitch * ny elements
+  int32_t bc[4];                 // west, east, south, north
+  int64_t sx0, sy0, sx1, sy1;    // solid square [sx0, sx1) x [sy0, sy1); empty if sx1 <= sx0
+  double feq_in[9];              // inlet quasiequilibrium (FP64; cast at use)
+  double beta2;                  // 2 beta
+  double delta;                  // Ehrenfests' tolerance
+  int32_t ds_on;                 // 0 when delta = +inf: no Delta S work at all
+  int32_t kmax;                  // k
+};
+
+__device__ __forceinline__ bool is_solid(const Geom& g, int64_t x, int64_t y) {
+  return x >= g.sx0 && x < g.sx1 && y >= g.sy0 && y < g.sy1;
+}
+
+// ---------------------------------------------------------------------------
+// Moments and quasiequilibria (evaluated in T = float or double)
+// ---------------------------------------------------------------------------
+template <int Q, typename T> struct Moments {
+  T rho, jx, jy, e2;
+};
+
+template <int Q, typename T>
+__device__ __forceinline__ Moments<Q, T> moments(const T* f) {
+  Moments<Q, T> m;
+  if constexpr (Q == 9) {
+    // fixed summation order i = 0..8
+    m.rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    m.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    m.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    m.e2 = (f[1] + f[2] + f[3] + f[4]) + T(2) * (f[5] + f[6] + f[7] + f[8]);
+  } else {
+    m.rho = f[0] + f[1] + f[2];
+    m.jx = f[2] - f[1];
+    m.jy = T(0);
+    m.e2 = f[1] + f[2];
+  }
+  return m;
+}
+
+// Polynomial quasiequilibrium.  D1Q3: Sec. 4.1's formulas.  D2Q9: the
+// second-order polynomial W_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u) of the
+// LBGK literature the paper cites for it.
+template <int Q, typename T>
+__device__ __forceinline__ void qe_poly(T rho, T ux, T uy, T* fs) {
+  if constexpr (Q == 9) {
+    const T uu = ux * ux + uy * uy;
+    const T base = T(1) - T(1.5) * uu;  // 1 - 3/2 u.u
+    const T r0 = rho * T(4.0 / 9.0), r1 = rho * T(1.0 / 9.0), r2 = rho * T(1.0 / 36.0);
+    fs[0] = r0 * base;
+    // axis velocities: c.u = +-ux, +-uy
+    const T ax = base + T(4.5) * ux * ux, ay = base + T(4.5) * uy * uy;
+    fs[1] = r1 * (ax + T(3) * ux);
+    fs[3] = r1 * (ax - T(3) * ux);
+    fs[2] = r1 * (ay + T(3) * uy);
+    fs[4] = r1 * (ay - T(3) * uy);
+    // diagonals: c.u = +-(ux + uy), +-(ux - uy)
+    const T p = ux + uy, q = ux - uy;
+    const T dp = base + T(4.5) * p * p, dq = base + T(4.5) * q * q;
+    fs[5] = r2 * (dp + T(3) * p);  // NE  (+1,+1)
+    fs[7] = r2 * (dp - T(3) * p);  // SW  (-1,-1)
+    fs[8] = r2 * (dq + T(3) * q);  // SE  (+1,-1)
+    fs[6] = r2 * (dq - T(3) * q);  // NW  (-1,+1)
+  } else {
+    const T u = ux;
+    fs[0] = (T(2) * rho / T(3)) * (T(1) - T(1.5) * u * u);
+    fs[1] = (rho / T(6)) * (T(1) - T(3) * u + T(3) * u * u);
+    fs[2] = (rho / T(6)) * (T(1) + T(3) * u + T(3) * u * u);
+  }
+}
+
+// Entropic quasiequilibrium with mass and momentum constraints, closed
+// form: D2Q9 product formula of Sec. 4.2; D1Q3 its 1-D factor (Sec. 4.1's
+// explicit formulas with the right-hand sides of f2 and f3 in the order that
+// reproduces +rho u).
+template <typename T> __device__ __forceinline__ T dsqrt(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_sqrtf(x);
+  else return __builtin_sqrt(x);
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void qe_entropic_mm(T rho, T ux, T uy, T* fs) {
+  const T sx = dsqrt(T(1) + T(3) * ux * ux);
+  const T ax = T(2) - sx;                      // weight factor of the rest component
+  const T bx = (T(2) * ux + sx) / (T(1) - ux);  // X = factor of a +1 component
+  if constexpr (Q == 3) {
+    // rho (2/3, 1/6, 1/6) * (2 - s) * X^{v}
+    const T base = rho * ax;
+    fs[0] = base * T(2.0 / 3.0);
+    fs[1] = base * T(1.0 / 6.0) / bx;
+    fs[2] = base * T(1.0 / 6.0) * bx;
+  } else {
+    const T sy = dsqrt(T(1) + T(3) * uy * uy);
+    const T ay = T(2) - sy;
+    const T by = (T(2) * uy + sy) / (T(1) - uy);
+    const T ibx = T(1) / bx, iby = T(1) / by;
+    const T base = rho * ax * ay;
+    const T b1 = base * T(1.0 / 9.0), b2 = base * T(1.0 / 36.0);
+    fs[0] = base * T(4.0 / 9.0);
+    fs[1] = b1 * bx;
+    fs[3] = b1 * ibx;
+    fs[2] = b1 * by;
+    fs[4] = b1 * iby;
+    fs[5] = b2 * bx * by;
+    fs[6] = b2 * ibx * by;
+    fs[7] = b2 * ibx * iby;
+    fs[8] = b2 * bx * iby;
+  }
+}
+
+template <int Q, int QE, typename T>
+__device__ __forceinline__ void qe_eval(const Moments<Q, T>& m, T* fs) {
+  T inv;
+  if constexpr (sizeof(T) == 4) inv = __builtin_amdgcn_rcpf(m.rho);
+  else inv = T(1) / m.rho;
+  const T ux = m.jx * inv, uy = m.jy * inv;
+  if constexpr (QE == QE_POLY) qe_poly<Q, T>(m.rho, ux, uy, fs);
+  else qe_entropic_mm<Q, T>(m.rho, ux, uy, fs);
+}
+
+// ---------------------------------------------------------------------------
+// Nonequilibrium entropy
+// ---------------------------------------------------------------------------
+// Per population, with s = (f - f*)/(f + f*), sigma = f + f*:
+//   f ln(f/f*) - f + f* = sigma s^2 [1 + s (1 + s) G(s^2)],
+//   G(t) = sum_{j >= 0} t^j / (2j + 3)
+// (from the series of artanh; every term is non-negative, no cancellation).
+
+// FP32 screen: returns a value that is >= Delta S (1 - 2e-3) up to FP32
+// rounding for sites with every |s| <= 1/2, and +inf when some |s| > 1/2,
+// some f < 0, f* <= 0, or a value is not finite.  The caller re-evaluates
+// screened sites in FP64.
+template <int Q>
+__device__ __forceinline__ float dS_screen(const float* f, const float* fs) {
+  float acc = 0.0f;
+  bool wild = false;
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float a = f[i], b = fs[i];
+    const float d = a - b, sg = a + b;
+    const float s = d * __builtin_amdgcn_rcpf(sg);
+    const float t = s * s;
+    const float h = 1.0f + (s + t) * (1.0f / 3.0f + t * (0.2f + t * (1.0f / 7.0f)));
+    acc += (d * s) * h;
+    wild |= !(a >= 0.0f) | !(b > 0.0f) | !(__builtin_fabsf(s) <= 0.5f);
+  }
+  return wild ? __builtin_inff() : acc;
+}
+
+// FP64 Delta S (Sec. 3.3 Kullback form, generalised by -f + f* so that it
+// stays >= 0 when masses differ by round-off); +inf for f < 0 or f* <= 0.
+template <int Q>
+__device__ __forceinline__ double dS_fp64(const double* f, const double* fs) {
+  double acc = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    const double a = f[i], b = fs[i];
+    if (!(a >= 0.0) || !(b > 0.0)) return __builtin_inf();
+    if (a == 0.0) { acc += b; continue; }
+    const double sg = a + b, s = (a - b) / sg;
+    if (__builtin_fabs(s) <= 0.25) {
+      const double t = s * s;
+      double G = 1.0 / 29.0;
+      // Horner for G(t) = sum_{j=0}^{13} t^j / (2j + 3); t <= 1/16
+      G = G * t + 1.0 / 27.0;
+      G = G * t + 1.0 / 25.0;
+      G = G * t + 1.0 / 23.0;
+      G = G * t + 1.0 / 21.0;
+      G = G * t + 1.0 / 19.0;
+      G = G * t + 1.0 / 17.0;
+      G = G * t + 1.0 / 15.0;
+      G = G * t + 1.0 / 13.0;
+      G = G * t + 1.0 / 11.0;
+      G = G * t + 1.0 / 9.0;
+      G = G * t + 1.0 / 7.0;
+      G = G * t + 1.0 / 5.0;
+      G = G * t + 1.0 / 3.0;
+      acc += sg * t * (1.0 + s * (1.0 + s) * G);
+    } else {
+      acc += a * ::log(a / b) - a + b;
+    }
+  }
+  return acc;
+}
+
+}  // namespace lbm

@@ -1,0 +1,606 @@
+// lbm_kernels.hip -- gfx950 kernels of the Ehrenfests'-step regularised LBGK
+// time step (Sec. 3.2, eq. (ESLB) of Sec. 4.1, boundary rules of Sec. 4.2).
+//
+// One time step is four kernels on one stream:
+//   k_step   fused pull-stream + boundary rules + moments + f* + FP32 Delta S
+//            screen + LBGK collision + write; screened sites are appended to
+//            a list (one atomic per wavefront); FP64 block partials of the
+//            moments for the conservation sums.            (HBM bound)
+//   k_rank   FP64 Delta S of the screened sites; sites with Delta S > delta
+//            become candidates (site, Delta S) and feed a 2^15-bin histogram
+//            of the top bits of Delta S.                    (O(#screened))
+//   k_select one workgroup: "fewer than k: all of them", otherwise the k
+//            largest (Delta S descending, site ascending) by the histogram
+//            bin and an 8-bit radix refinement of the remaining 80 key bits.
+//   k_reset  selected sites: re-pull f(x, t), recompute f*, overwrite the
+//            collided values with f* (return to quasiequilibrium).
+//
+// State layout: population planes [Q][ny][pitch] of T (float or double),
+// x fastest, pitch a multiple of 64 elements.  The state buffer holds the
+// post-collision populations f'(x, t-1) at their origin site ("pull"
+// layout); right after init or set_populations it holds the pre-collision
+// f(x, t) itself ("canonical" layout) and the first step reads it in place.
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.hpp"
+#include "lbm_launch.hpp"
+
+namespace lbm {
+
+// logical block index for a hardware block id: hardware dispatch deals
+// blocks round-robin over the 8 XCDs, so consecutive logical tiles (which
+// share halo cache lines) are given to the same XCD and its L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t per = nb >> 3, rem = nb & 7, xcd = b & 7, idx = b >> 3;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// f_i(x, y, t) from the post-collision state with the boundary rules:
+// x outside: periodic wrap | inlet quasiequilibrium | zero-gradient (the
+// value the adjacent inner column receives); y outside: periodic wrap |
+// free-slip (specular: the vertically mirrored population leaving from
+// (x - cx, y)) | zero-gradient; source in the solid: halfway bounce-back.
+template <typename T, int Q>
+__device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g, int64_t x, int64_t y,
+                                          int i) {
+  const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i];
+  for (int it = 0; it < 4; ++it) {
+    int64_t sx = x - cx, sy = y - cy;
+    int j = i;
+    if (sx < 0 || sx >= g.nx) {
+      const int b = sx < 0 ? g.bc[0] : g.bc[1];
+      if (b == BC_PERIODIC) sx = sx < 0 ? sx + g.nx : sx - g.nx;
+      else if (b == BC_INLET_EQ) return T(g.feq_in[i]);
+      else { x = sx < 0 ? x + 1 : x - 1; continue; }
+    }
+    if (sy < 0 || sy >= g.ny) {
+      const int b = sy < 0 ? g.bc[2] : g.bc[3];
+      if (b == BC_PERIODIC) sy = sy < 0 ? sy + g.ny : sy - g.ny;
+      else if (b == BC_FREESLIP) { j = Lat<Q>::mir[i]; sy = y; }
+      else if (b == BC_INLET_EQ) return T(g.feq_in[i]);
+      else { y = sy < 0 ? y + 1 : y - 1; continue; }
+    }
+    if (is_solid(g, sx, sy)) { j = Lat<Q>::opp[i]; sx = x; sy = y; }
+    return A[(int64_t)j * g.plane + sy * g.pitch + sx];
+  }
+  return T(0);
+}
+
+// canonical pre-collision populations of one fluid site
+template <typename T, int Q, bool PULL>
+__device__ __forceinline__ void load_site(const T* __restrict__ A, const Geom& g, int64_t x, int64_t y,
+                                          T* f) {
+  #pragma unroll
+  for (int i = 0; i < Q; ++i)
+    f[i] = PULL ? pull_general<T, Q>(A, g, x, y, i) : A[(int64_t)i * g.plane + y * g.pitch + x];
+}
+
+// ---------------------------------------------------------------------------
+// k_step
+// ---------------------------------------------------------------------------
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
+  const T* __restrict__ A = (const T*)a.A;
+  T* __restrict__ B = (T*)a.B;
+  const Geom& g = a.g;
+  const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
+  const int64_t y = b / a.ntx;
+  const int64_t x0 = (b - y * a.ntx) * STEP_TX;
+  const int64_t x = x0 + threadIdx.x;
+  const bool fluid = x < g.nx && !is_solid(g, x, y);
+
+  T f[Q];
+  if (PULL) {
+    // tiles whose whole 3 x (STEP_TX + 2) neighbourhood is inside the lattice
+    // and clear of the solid pull directly (uniform branch per block)
+    const bool xin = x0 >= 1 && x0 + STEP_TX <= g.nx - 1;
+    const bool yin = (Q == 3) || (y >= 1 && y <= g.ny - 2);
+    const bool hit = x0 - 1 < g.sx1 && x0 + STEP_TX >= g.sx0 && y - 1 < g.sy1 && y + 1 >= g.sy0;
+    if (xin && yin && !hit) {
+      const int64_t o = y * g.pitch + x;
+      #pragma unroll
+      for (int i = 0; i < Q; ++i)
+        f[i] = A[(int64_t)i * g.plane + o - Lat<Q>::cy[i] * g.pitch - Lat<Q>::cx[i]];
+    } else if (fluid) {
+      load_site<T, Q, true>(A, g, x, y, f);
+    } else {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = T(Lat<Q>::w(i));
+    }
+  } else {
+    if (fluid) load_site<T, Q, false>(A, g, x, y, f);
+    else {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = T(Lat<Q>::w(i));
+    }
+  }
+
+  const Moments<Q, T> m = moments<Q, T>(f);
+  T fs[Q];
+  qe_eval<Q, QE, T>(m, fs);
+
+  // FP32 screen of Delta S; screened sites are re-ranked in FP64 by k_rank
+  bool scr = false;
+  if (g.ds_on && fluid) {
+    float ff[Q], fsf[Q];
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) { ff[i] = (float)f[i]; fsf[i] = (float)fs[i]; }
+    const float ds = dS_screen<Q>(ff, fsf);
+    const float thr = a.thr_a - a.thr_b * __builtin_sqrtf(fmaxf((float)m.rho, 0.0f));
+    scr = !(ds < thr);
+  }
+
+  // LBGK collision f' = f + 2 beta (f* - f), written at the origin site
+  if (fluid) {
+    const T b2 = T(g.beta2);
+    const int64_t o = y * g.pitch + x;
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = f[i] + b2 * (fs[i] - f[i]);
+  }
+
+  // append screened sites: one atomic per wavefront
+  const unsigned long long mask = __ballot(scr);
+  if (mask) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&a.ctr[C_SCREEN], (uint32_t)__popcll(mask));
+    base = (uint32_t)__shfl((int)base, leader);
+    if (scr) a.screen[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(x + y * g.nx);
+  }
+
+  // FP64 block partials of rho, rho u1, rho u2, 2E (pre-collision)
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (fluid) { s0 = (double)m.rho; s1 = (double)m.jx; s2 = (double)m.jy; s3 = (double)m.e2; }
+  #pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off);
+    s1 += __shfl_xor(s1, off);
+    s2 += __shfl_xor(s2, off);
+    s3 += __shfl_xor(s3, off);
+  }
+  __shared__ double red[STEP_TX / 64][4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[wv][0] = s0; red[wv][1] = s1; red[wv][2] = s2; red[wv][3] = s3; }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    #pragma unroll
+    for (int w = 0; w < STEP_TX / 64; ++w) s += red[w][threadIdx.x];
+    a.partials[b * 4 + threadIdx.x] = s;
+    if (!__builtin_isfinite(s)) atomicOr(&a.ctr[C_NONFINITE], 1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_rank: FP64 Delta S of screened sites
+// ---------------------------------------------------------------------------
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(256) void k_rank(StepArgs a) {
+  const T* __restrict__ A = (const T*)a.A;
+  const Geom& g = a.g;
+  const uint32_t n = a.ctr[C_SCREEN];
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
+    const uint32_t site = a.screen[t];
+    const int64_t y = site / g.nx, x = site - y * g.nx;
+    T fT[Q];
+    load_site<T, Q, PULL>(A, g, x, y, fT);
+    double fd[Q];
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) fd[i] = (double)fT[i];
+    const Moments<Q, double> m = moments<Q, double>(fd);
+    double fs[Q];
+    qe_eval<Q, QE, double>(m, fs);
+    const double ds = dS_fp64<Q>(fd, fs);
+    if (ds > g.delta) {
+      const uint32_t idx = atomicAdd(&a.ctr[C_CAND], 1u);
+      a.cand[idx] = Cand{site, 0u, ds};
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(ds);
+      atomicAdd(&a.hist[(bits >> 48) & (HIST_BINS - 1)], 1u);
+      if (__builtin_isinf(ds)) atomicAdd(&a.ctr[C_INVALID], 1u);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_select: at most k candidates, largest Delta S first, ties by lower site
+// ---------------------------------------------------------------------------
+// Key of a candidate: the 63 bits of its non-negative FP64 Delta S followed
+// by the 32 bits of ~site (a larger key = larger Delta S, then lower site).
+// Keys are unique, so "the k largest keys" is one well-defined set.
+__device__ __forceinline__ unsigned long long ds_bits(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
+__global__ __launch_bounds__(1024) void k_select(StepArgs a) {
+  __shared__ uint32_t s_scan[1024];
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_nsel, s_nbnd, s_bstar, s_r, s_dig, s_rr, s_exact;
+  __shared__ double s_max[16], s_min[16];
+  const int tid = threadIdx.x;
+  const uint32_t n = a.ctr[C_CAND];
+  const uint32_t k = (uint32_t)a.g.kmax;
+  double vmax = 0.0, vmin = __builtin_inf();
+  if (tid == 0) { s_nsel = 0; s_nbnd = 0; s_bstar = 0; s_r = 0; }
+  __syncthreads();
+
+  if (k == 0 || n <= k) {
+    for (uint32_t t = tid; t < n; t += 1024) {
+      const Cand c = a.cand[t];
+      vmax = fmax(vmax, c.ds);
+      if (k > 0) {
+        a.sel[t] = c.site;
+        a.sel_ds[t] = c.ds;
+        vmin = fmin(vmin, c.ds);
+      }
+    }
+    if (tid == 0) s_nsel = k > 0 ? n : 0;
+  } else {
+    // 1. the histogram bin that holds the k-th largest key; thread t owns
+    //    the 32 bins [HIST_BINS-1-32t-31, HIST_BINS-1-32t], top first
+    uint32_t local = 0;
+    for (int j = 0; j < 32; ++j) local += a.hist[HIST_BINS - 1 - 32 * tid - j];
+    s_scan[tid] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
+      __syncthreads();
+      s_scan[tid] += v;
+      __syncthreads();
+    }
+    const uint32_t incl = s_scan[tid], excl = incl - local;
+    if (excl < k && incl >= k) {
+      uint32_t c = excl;
+      for (int j = 0; j < 32; ++j) {
+        const uint32_t bin = HIST_BINS - 1 - 32 * tid - j;
+        const uint32_t h = a.hist[bin];
+        if (c + h >= k) { s_bstar = bin; s_r = k - c; break; }
+        c += h;
+      }
+    }
+    __syncthreads();
+    const uint32_t bstar = s_bstar;
+
+    // 2. keys in higher bins are selected; keys in the bin are refined
+    for (uint32_t t = tid; t < n; t += 1024) {
+      const Cand c = a.cand[t];
+      vmax = fmax(vmax, c.ds);
+      const uint32_t bin = (uint32_t)(ds_bits(c.ds) >> 48) & (HIST_BINS - 1);
+      if (bin > bstar) {
+        const uint32_t i = atomicAdd(&s_nsel, 1u);
+        if (i < k) { a.sel[i] = c.site; a.sel_ds[i] = c.ds; }
+        vmin = fmin(vmin, c.ds);
+      } else if (bin == bstar) {
+        a.bnd[atomicAdd(&s_nbnd, 1u)] = c;
+      }
+    }
+    __syncthreads();
+    const uint32_t m = s_nbnd;
+
+    // 3. 8-bit digits of the remaining key: Delta S bits 47..0, then ~site
+    unsigned long long Thi = 0, Mhi = 0;
+    uint32_t Tlo = 0, Mlo = 0, rr = s_r;
+    for (int pass = 0; pass < 10; ++pass) {
+      const bool inhi = pass < 6;
+      const int sh = inhi ? 40 - 8 * pass : 24 - 8 * (pass - 6);
+      if (tid < 256) s_hist[tid] = 0;
+      __syncthreads();
+      for (uint32_t t = tid; t < m; t += 1024) {
+        const Cand c = a.bnd[t];
+        const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
+        const uint32_t lo = ~c.site;
+        if ((hi & Mhi) == Thi && (lo & Mlo) == Tlo) {
+          const uint32_t d = inhi ? (uint32_t)(hi >> sh) & 255u : (lo >> sh) & 255u;
+          atomicAdd(&s_hist[d], 1u);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t c = 0;
+        for (int d = 255; d >= 0; --d) {
+          const uint32_t h = s_hist[d];
+          if (c + h >= rr) { s_dig = (uint32_t)d; s_rr = rr - c; s_exact = (h == rr - c); break; }
+          c += h;
+        }
+      }
+      __syncthreads();
+      const uint32_t d = s_dig;
+      rr = s_rr;
+      if (inhi) { Thi |= (unsigned long long)d << sh; Mhi |= 255ull << sh; }
+      else { Tlo |= d << sh; Mlo |= 255u << sh; }
+      const bool done = s_exact != 0;
+      __syncthreads();
+      if (done) break;
+    }
+
+    // 4. keys of the bin that are >= T (T's unfixed low bits are zero)
+    for (uint32_t t = tid; t < m; t += 1024) {
+      const Cand c = a.bnd[t];
+      const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
+      const uint32_t lo = ~c.site;
+      if (hi > Thi || (hi == Thi && lo >= Tlo)) {
+        const uint32_t i = atomicAdd(&s_nsel, 1u);
+        if (i < k) { a.sel[i] = c.site; a.sel_ds[i] = c.ds; }
+        vmin = fmin(vmin, c.ds);
+      }
+    }
+  }
+
+  // block max / min
+  #pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    vmax = fmax(vmax, __shfl_xor(vmax, off));
+    vmin = fmin(vmin, __shfl_xor(vmin, off));
+  }
+  if ((tid & 63) == 0) { s_max[tid >> 6] = vmax; s_min[tid >> 6] = vmin; }
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0, mn = __builtin_inf();
+    for (int w = 0; w < 16; ++w) { mx = fmax(mx, s_max[w]); mn = fmin(mn, s_min[w]); }
+    const uint32_t nsel = s_nsel < k ? s_nsel : k;  // == k by construction
+    a.st->n_above = n;
+    a.st->n_sel = nsel;
+    a.st->n_invalid = a.ctr[C_INVALID];
+    a.st->total_sel += nsel;
+    a.st->max = n ? mx : 0.0;
+    a.st->kth = nsel ? mn : 0.0;
+    a.ctr[C_NSEL] = nsel;
+    a.ctr[C_SCREEN] = 0;
+    a.ctr[C_CAND] = 0;
+    a.ctr[C_INVALID] = 0;
+  }
+  // clear the histogram for the next step
+  if (n > 0)
+    for (int j = tid; j < HIST_BINS; j += 1024) a.hist[j] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_reset: Ehrenfests' step at the selected sites
+// ---------------------------------------------------------------------------
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(64) void k_reset(StepArgs a) {
+  const uint32_t n = a.ctr[C_NSEL];
+  const uint32_t t = blockIdx.x * 64u + threadIdx.x;
+  if (t >= n) return;
+  const T* __restrict__ A = (const T*)a.A;
+  T* __restrict__ B = (T*)a.B;
+  const Geom& g = a.g;
+  const uint32_t site = a.sel[t];
+  const int64_t y = site / g.nx, x = site - y * g.nx;
+  T f[Q];
+  load_site<T, Q, PULL>(A, g, x, y, f);
+  const Moments<Q, T> m = moments<Q, T>(f);
+  T fs[Q];
+  qe_eval<Q, QE, T>(m, fs);
+  const int64_t o = y * g.pitch + x;
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = fs[i];
+}
+
+// ---------------------------------------------------------------------------
+// initial state, population access, moments, sums, clearing
+// ---------------------------------------------------------------------------
+template <typename T, int Q, int QE>
+__global__ __launch_bounds__(256) void k_init(StepArgs a, const double* __restrict__ rho0,
+                                              const double* __restrict__ u0) {
+  T* __restrict__ S = (T*)a.B;
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    const int64_t y = s / g.nx, x = s - y * g.nx;
+    double fs[Q];
+    if (is_solid(g, x, y)) {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) fs[i] = 0.0;
+    } else {
+      const double rho = rho0[s], ux = u0[s], uy = Q == 9 ? u0[N + s] : 0.0;
+      if (QE == QE_POLY) qe_poly<Q, double>(rho, ux, uy, fs);
+      else qe_entropic_mm<Q, double>(rho, ux, uy, fs);
+    }
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) S[(int64_t)i * g.plane + y * g.pitch + x] = (T)fs[i];
+  }
+}
+
+template <typename T, int Q, bool PULL>
+__global__ __launch_bounds__(256) void k_get(StepArgs a, T* __restrict__ out) {
+  const T* __restrict__ A = (const T*)a.A;
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    const int64_t y = s / g.nx, x = s - y * g.nx;
+    T f[Q];
+    if (is_solid(g, x, y)) {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = T(0);
+    } else {
+      load_site<T, Q, PULL>(A, g, x, y, f);
+    }
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) out[(int64_t)i * N + s] = f[i];
+  }
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(256) void k_set(StepArgs a, const T* __restrict__ in) {
+  T* __restrict__ S = (T*)a.B;
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  bool bad = false;
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    const int64_t y = s / g.nx, x = s - y * g.nx;
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const T v = in[(int64_t)i * N + s];
+      bad |= !__builtin_isfinite(v);
+      S[(int64_t)i * g.plane + y * g.pitch + x] = v;
+    }
+  }
+  if (bad) atomicOr(&a.ctr[C_NONFINITE + 2], 1u);
+}
+
+template <typename T, int Q, bool PULL>
+__global__ __launch_bounds__(256) void k_moments(StepArgs a, double* __restrict__ rho,
+                                                 double* __restrict__ rhou, double* __restrict__ e2) {
+  const T* __restrict__ A = (const T*)a.A;
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    const int64_t y = s / g.nx, x = s - y * g.nx;
+    double fd[Q];
+    if (is_solid(g, x, y)) {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) fd[i] = 0.0;
+    } else {
+      T f[Q];
+      load_site<T, Q, PULL>(A, g, x, y, f);
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) fd[i] = (double)f[i];
+    }
+    const Moments<Q, double> m = moments<Q, double>(fd);
+    if (rho) rho[s] = m.rho;
+    if (rhou) { rhou[s] = m.jx; rhou[N + s] = m.jy; }
+    if (e2) e2[s] = m.e2;
+  }
+}
+
+// fixed-order reduction of the block partials of the last step
+__global__ __launch_bounds__(256) void k_finalize(StepArgs a) {
+  __shared__ double red[4][256];
+  const int tid = threadIdx.x;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t b = tid; b < a.nblocks; b += 256)
+    for (int c = 0; c < 4; ++c) s[c] += a.partials[b * 4 + c];
+  for (int c = 0; c < 4; ++c) red[c][tid] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int c = 0; c < 4; ++c) red[c][tid] += red[c][tid + w];
+    __syncthreads();
+  }
+  if (tid < 4) a.st->sums[tid] = red[tid][0];
+}
+
+__global__ __launch_bounds__(256) void k_clear(StepArgs a) {
+  const int64_t t0 = blockIdx.x * 256ll + threadIdx.x, stride = (int64_t)gridDim.x * 256;
+  for (int64_t j = t0; j < HIST_BINS; j += stride) a.hist[j] = 0;
+  for (int64_t j = t0; j < a.nblocks * 4; j += stride) a.partials[j] = 0.0;
+  if (t0 < C_COUNT) a.ctr[t0] = 0;
+  if (t0 == 0) {
+    a.st->n_above = a.st->n_sel = a.st->n_invalid = a.st->total_sel = 0;
+    a.st->kth = a.st->max = 0.0;
+    for (int c = 0; c < 4; ++c) a.st->sums[c] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <typename T, int Q, int QE, bool PULL>
+static hipError_t step_t(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0) { hipError_t e = hipEventRecord(ev0, s); if (e != hipSuccess) return e; }
+  hipLaunchKernelGGL((k_step<T, Q, QE, PULL>), dim3((unsigned)a.nblocks), dim3(STEP_TX), 0, s, a);
+  if (ev1) { hipError_t e = hipEventRecord(ev1, s); if (e != hipSuccess) return e; }
+  if (a.g.ds_on) {
+    hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(512), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, a);
+    if (a.g.kmax > 0)
+      hipLaunchKernelGGL((k_reset<T, Q, QE, PULL>), dim3((unsigned)((a.g.kmax + 63) / 64)), dim3(64), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int Q, int QE>
+static hipError_t step_p(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return pull ? step_t<T, Q, QE, true>(a, s, e0, e1) : step_t<T, Q, QE, false>(a, s, e0, e1);
+}
+
+template <typename T, int Q>
+static hipError_t step_q(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return a.qe == QE_POLY ? step_p<T, Q, QE_POLY>(a, pull, s, e0, e1)
+                         : step_p<T, Q, QE_ENTROPIC_MM>(a, pull, s, e0, e1);
+}
+
+template <typename T>
+static hipError_t step_T(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return a.Q == 9 ? step_q<T, 9>(a, pull, s, e0, e1) : step_q<T, 3>(a, pull, s, e0, e1);
+}
+
+hipError_t launch_step(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  return a.prec == 1 ? step_T<double>(a, pull, s, ev0, ev1) : step_T<float>(a, pull, s, ev0, ev1);
+}
+
+static unsigned site_grid(const StepArgs& a) {
+  const int64_t N = a.g.nx * a.g.ny;
+  int64_t nb = (N + 255) / 256;
+  return (unsigned)(nb < 8192 ? (nb > 0 ? nb : 1) : 8192);
+}
+
+template <typename T, int Q, int QE>
+static void init_t(const StepArgs& a, const double* rho0, const double* u0, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<T, Q, QE>), dim3(site_grid(a)), dim3(256), 0, s, a, rho0, u0);
+}
+
+hipError_t launch_init(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,
+                       hipStream_t s) {
+  (void)twoE0;
+  if (a.prec == 1) {
+    if (a.Q == 9) { if (a.qe == QE_POLY) init_t<double, 9, QE_POLY>(a, rho0, u0, s); else init_t<double, 9, QE_ENTROPIC_MM>(a, rho0, u0, s); }
+    else { if (a.qe == QE_POLY) init_t<double, 3, QE_POLY>(a, rho0, u0, s); else init_t<double, 3, QE_ENTROPIC_MM>(a, rho0, u0, s); }
+  } else {
+    if (a.Q == 9) { if (a.qe == QE_POLY) init_t<float, 9, QE_POLY>(a, rho0, u0, s); else init_t<float, 9, QE_ENTROPIC_MM>(a, rho0, u0, s); }
+    else { if (a.qe == QE_POLY) init_t<float, 3, QE_POLY>(a, rho0, u0, s); else init_t<float, 3, QE_ENTROPIC_MM>(a, rho0, u0, s); }
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int Q>
+static void get_t(const StepArgs& a, bool pull, void* out, hipStream_t s) {
+  if (pull) hipLaunchKernelGGL((k_get<T, Q, true>), dim3(site_grid(a)), dim3(256), 0, s, a, (T*)out);
+  else hipLaunchKernelGGL((k_get<T, Q, false>), dim3(site_grid(a)), dim3(256), 0, s, a, (T*)out);
+}
+
+hipError_t launch_get(const StepArgs& a, bool pull, void* out, hipStream_t s) {
+  if (a.prec == 1) { if (a.Q == 9) get_t<double, 9>(a, pull, out, s); else get_t<double, 3>(a, pull, out, s); }
+  else { if (a.Q == 9) get_t<float, 9>(a, pull, out, s); else get_t<float, 3>(a, pull, out, s); }
+  return hipGetLastError();
+}
+
+hipError_t launch_set(const StepArgs& a, const void* in, hipStream_t s) {
+  const unsigned gr = site_grid(a);
+  if (a.prec == 1) {
+    if (a.Q == 9) hipLaunchKernelGGL((k_set<double, 9>), dim3(gr), dim3(256), 0, s, a, (const double*)in);
+    else hipLaunchKernelGGL((k_set<double, 3>), dim3(gr), dim3(256), 0, s, a, (const double*)in);
+  } else {
+    if (a.Q == 9) hipLaunchKernelGGL((k_set<float, 9>), dim3(gr), dim3(256), 0, s, a, (const float*)in);
+    else hipLaunchKernelGGL((k_set<float, 3>), dim3(gr), dim3(256), 0, s, a, (const float*)in);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int Q>
+static void mom_t(const StepArgs& a, bool pull, double* r, double* ru, double* e, hipStream_t s) {
+  if (pull) hipLaunchKernelGGL((k_moments<T, Q, true>), dim3(site_grid(a)), dim3(256), 0, s, a, r, ru, e);
+  else hipLaunchKernelGGL((k_moments<T, Q, false>), dim3(site_grid(a)), dim3(256), 0, s, a, r, ru, e);
+}
+
+hipError_t launch_moments(const StepArgs& a, bool pull, double* rho, double* rhou, double* e2,
+                          hipStream_t s) {
+  if (a.prec == 1) { if (a.Q == 9) mom_t<double, 9>(a, pull, rho, rhou, e2, s); else mom_t<double, 3>(a, pull, rho, rhou, e2, s); }
+  else { if (a.Q == 9) mom_t<float, 9>(a, pull, rho, rhou, e2, s); else mom_t<float, 3>(a, pull, rho, rhou, e2, s); }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear(const StepArgs& a, hipStream_t s) {
+  int64_t n = a.nblocks * 4 > HIST_BINS ? a.nblocks * 4 : HIST_BINS;
+  int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_clear, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

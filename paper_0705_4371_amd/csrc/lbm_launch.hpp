@@ -1,0 +1,71 @@
+// lbm_launch.hpp -- host-side launch interface between the C-ABI layer and
+// the step kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+// candidate of the Ehrenfests' ranking: site and its FP64 Delta S
+struct Cand {
+  uint32_t site;
+  uint32_t pad;
+  double ds;
+};
+
+// device-side statistics written by the selection kernel
+struct DevStats {
+  unsigned long long n_above, n_sel, n_invalid, total_sel;
+  double kth, max;
+  double sums[4];
+};
+
+// device counters (uint32 each)
+enum : int {
+  C_SCREEN = 0,    // sites that passed the FP32 screen this step
+  C_CAND = 1,      // sites with FP64 Delta S > delta this step
+  C_INVALID = 2,   // candidates with Delta S = +inf
+  C_NONFINITE = 3, // sticky: a non-finite moment sum was seen
+  C_NSEL = 4,      // sites selected this step (read by the reset kernel)
+  C_COUNT = 8
+};
+
+constexpr int HIST_BITS = 15;
+constexpr int HIST_BINS = 1 << HIST_BITS;
+constexpr int STEP_TX = 256;  // sites per step-kernel block (one row segment)
+
+struct StepArgs {
+  const void* A;   // state read this step
+  void* B;         // state written this step
+  Geom g;
+  uint32_t* ctr;
+  uint32_t* screen;
+  Cand* cand;
+  Cand* bnd;
+  uint32_t* hist;
+  uint32_t* sel;
+  double* sel_ds;
+  DevStats* st;
+  double* partials;
+  float thr_a, thr_b;  // FP32 screen threshold: thr_a - thr_b * sqrt(rho)
+  int64_t ntx, nblocks;
+  int prec, Q, qe;
+};
+
+// launch one step's kernels (fused step, rank, select, reset) on stream s;
+// ev0/ev1 (optional) bracket the fused step kernel
+hipError_t launch_step(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+
+hipError_t launch_init(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,
+                       hipStream_t s);
+hipError_t launch_get(const StepArgs& a, bool pull, void* out, hipStream_t s);
+hipError_t launch_set(const StepArgs& a, const void* in, hipStream_t s);
+hipError_t launch_moments(const StepArgs& a, bool pull, double* rho, double* rhou, double* e2,
+                          hipStream_t s);
+hipError_t launch_finalize(const StepArgs& a, hipStream_t s);
+hipError_t launch_clear(const StepArgs& a, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,226 @@
+"""Thin Python binding of the C ABI in include/lbm.h.
+
+Argument marshalling only: every step of the method runs in the gfx950
+kernels of ``liblbm.so``.  PyTorch provides device memory and the stream.
+The functions keep the C names; ``Lattice`` is a small convenience wrapper
+that owns a context.  If ``liblbm.so`` is missing the import of this module
+raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from . import _build
+
+LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE, LBM_E_NOCONV, LBM_E_STATE = \
+    0, -1, -2, -3, -4, -5, -6
+LBM_D1Q3, LBM_D2Q9 = 3, 9
+LBM_QE_POLY, LBM_QE_ENTROPIC_MM, LBM_QE_ENTROPIC_M = 0, 1, 2
+LBM_FP32, LBM_FP64 = 0, 1
+LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ = 0, 1, 2, 3
+LBM_COLL_LBGK, LBM_COLL_ELBM = 0, 1
+LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP = 0, 1, 2
+
+
+class lbm_config(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int32), ("qe", C.c_int32), ("precision", C.c_int32), ("collision", C.c_int32),
+        ("nx", C.c_int64), ("ny", C.c_int64),
+        ("nu", C.c_double), ("delta", C.c_double),
+        ("k", C.c_int32), ("fstar_start", C.c_int32),
+        ("bc", C.c_int32 * 4),
+        ("inlet_rho", C.c_double), ("inlet_u", C.c_double * 2),
+        ("solid_x0", C.c_int64), ("solid_y0", C.c_int64), ("solid_w", C.c_int64), ("solid_h", C.c_int64),
+        ("net", C.c_void_p), ("stream", C.c_void_p),
+    ]
+
+
+class lbm_es_stats(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("n_above_delta", C.c_int64), ("n_selected", C.c_int64),
+        ("n_invalid", C.c_int64), ("n_fallback", C.c_int64), ("total_selected", C.c_int64),
+        ("nonfinite", C.c_int64), ("pad0", C.c_int64),
+        ("kth_dS", C.c_double), ("max_dS", C.c_double), ("mass", C.c_double),
+        ("mom", C.c_double * 2), ("energy", C.c_double),
+    ]
+
+
+# name -> (restype, argtypes); the exported symbols of include/lbm.h
+_P = C.c_void_p
+SIGNATURES = {
+    "lbm_config_default": (None, [C.POINTER(lbm_config)]),
+    "lbm_validate_config": (C.c_int, [C.POINTER(lbm_config)]),
+    "lbm_init": (C.c_int, [C.POINTER(lbm_config), _P, _P, _P, C.POINTER(_P)]),
+    "lbm_step": (C.c_int, [_P, C.c_int64]),
+    "lbm_moments": (C.c_int, [_P, _P, _P, _P]),
+    "lbm_get_populations": (C.c_int, [_P, _P]),
+    "lbm_set_populations": (C.c_int, [_P, _P]),
+    "lbm_ehrenfest_stats": (C.c_int, [_P, C.POINTER(lbm_es_stats), _P, _P, C.c_int64]),
+    "lbm_candidates": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    "lbm_set_timing": (C.c_int, [_P, C.c_int]),
+    "lbm_kernel_time": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "lbm_layout": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "lbm_struct_sizes": (None, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "lbm_free": (None, [_P]),
+    "lbm_strerror": (C.c_char_p, [C.c_int]),
+    "lbm_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise RuntimeError("liblbm.so is not built (run __graft_entry__.build()); "
+                               "there is no CPU fallback for the GPU path")
+        L = C.CDLL(_build.LIB)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        a, b = C.c_int64(), C.c_int64()
+        L.lbm_struct_sizes(C.byref(a), C.byref(b))
+        if (a.value, b.value) != (C.sizeof(lbm_config), C.sizeof(lbm_es_stats)):
+            raise RuntimeError("struct layout mismatch between lbm.h and the binding")
+        _lib = L
+    return _lib
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        L = load()
+        msg = L.lbm_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%d): %s" % (where, L.lbm_strerror(code).decode(), code, msg))
+        self.code = code
+
+
+def check(code: int, where: str) -> None:
+    if code != LBM_OK:
+        raise LbmError(code, where)
+
+
+def make_config(lattice=LBM_D2Q9, qe=LBM_QE_POLY, precision=LBM_FP32, nx=64, ny=64, nu=1e-3,
+                delta=math.inf, k=0, bc=(LBM_BC_PERIODIC,) * 4, inlet_rho=1.0, inlet_u=(0.0, 0.0),
+                solid=(0, 0, 0, 0), collision=LBM_COLL_LBGK, fstar_start=LBM_START_DEFAULT,
+                stream=None) -> lbm_config:
+    c = lbm_config()
+    load().lbm_config_default(C.byref(c))
+    c.lattice, c.qe, c.precision, c.collision = lattice, qe, precision, collision
+    c.nx, c.ny, c.nu, c.delta, c.k = nx, ny, nu, delta, k
+    for i in range(4):
+        c.bc[i] = bc[i]
+    c.inlet_rho = inlet_rho
+    c.inlet_u[0], c.inlet_u[1] = inlet_u
+    c.solid_x0, c.solid_y0, c.solid_w, c.solid_h = solid
+    c.fstar_start = fstar_start
+    c.stream = stream
+    return c
+
+
+def config_from_workload(d: dict, precision: int, stream=None) -> lbm_config:
+    """Config from a workloads.* parameter dict (keys Q, qe, nx, ny, nu, ...)."""
+    return make_config(lattice=d["Q"], qe=d.get("qe", LBM_QE_POLY), precision=precision,
+                       nx=d["nx"], ny=d["ny"], nu=d["nu"], delta=d.get("delta", math.inf),
+                       k=d.get("k", 0), bc=d.get("bc", (LBM_BC_PERIODIC,) * 4),
+                       inlet_rho=d.get("inlet_rho", 1.0), inlet_u=d.get("inlet_u", (0.0, 0.0)),
+                       solid=d.get("solid", (0, 0, 0, 0)), stream=stream)
+
+
+class Lattice:
+    """Owns one lbm_ctx.  Tensors are torch CUDA tensors; host results numpy."""
+
+    def __init__(self, cfg: lbm_config, rho0, u0, twoE0=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.Q = cfg.lattice
+        self.dtype = torch.float64 if cfg.precision == LBM_FP64 else torch.float32
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        if cfg.stream is None:
+            cfg.stream = torch.cuda.current_stream().cuda_stream
+        self.stream_handle = cfg.stream
+        r = torch.as_tensor(np.ascontiguousarray(rho0, np.float64), device=self.dev)
+        u = torch.as_tensor(np.ascontiguousarray(u0, np.float64), device=self.dev)
+        e = None if twoE0 is None else torch.as_tensor(np.ascontiguousarray(twoE0, np.float64),
+                                                       device=self.dev)
+        ctx = C.c_void_p()
+        check(load().lbm_init(C.byref(cfg), r.data_ptr(), u.data_ptr(),
+                              e.data_ptr() if e is not None else None, C.byref(ctx)), "lbm_init")
+        self.ctx = ctx
+        torch.cuda.synchronize()  # the initial fields may be released after this
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().lbm_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.Q, self.cfg.ny, self.cfg.nx)
+
+    def step(self, n: int = 1) -> None:
+        check(load().lbm_step(self.ctx, n), "lbm_step")
+
+    def get_populations(self):
+        t = self.torch.empty(self.shape, dtype=self.dtype, device=self.dev)
+        check(load().lbm_get_populations(self.ctx, t.data_ptr()), "lbm_get_populations")
+        return t
+
+    def set_populations(self, f) -> None:
+        t = self.torch.as_tensor(f, dtype=self.dtype, device=self.dev).contiguous()
+        assert tuple(t.shape) == self.shape
+        check(load().lbm_set_populations(self.ctx, t.data_ptr()), "lbm_set_populations")
+
+    def moments(self):
+        ny, nx = self.cfg.ny, self.cfg.nx
+        rho = self.torch.empty((ny, nx), dtype=self.torch.float64, device=self.dev)
+        ru = self.torch.empty((2, ny, nx), dtype=self.torch.float64, device=self.dev)
+        e2 = self.torch.empty((ny, nx), dtype=self.torch.float64, device=self.dev)
+        check(load().lbm_moments(self.ctx, rho.data_ptr(), ru.data_ptr(), e2.data_ptr()), "lbm_moments")
+        return rho, ru, e2
+
+    def stats(self, sel_cap: int = 0):
+        st = lbm_es_stats()
+        sel = np.zeros(max(sel_cap, 1), np.int64)
+        ds = np.zeros(max(sel_cap, 1), np.float64)
+        check(load().lbm_ehrenfest_stats(self.ctx, C.byref(st), sel.ctypes.data, ds.ctypes.data,
+                                         sel_cap), "lbm_ehrenfest_stats")
+        n = min(sel_cap, st.n_selected)
+        return st, sel[:n], ds[:n]
+
+    def candidates(self):
+        n = C.c_int64()
+        check(load().lbm_candidates(self.ctx, None, None, 0, C.byref(n)), "lbm_candidates")
+        sites = np.zeros(max(n.value, 1), np.int64)
+        ds = np.zeros(max(n.value, 1), np.float64)
+        check(load().lbm_candidates(self.ctx, sites.ctypes.data, ds.ctypes.data, n.value, C.byref(n)),
+              "lbm_candidates")
+        return sites[:n.value], ds[:n.value]
+
+    def set_timing(self, on: bool) -> None:
+        check(load().lbm_set_timing(self.ctx, int(on)), "lbm_set_timing")
+
+    def kernel_time(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        check(load().lbm_kernel_time(self.ctx, C.byref(ms), C.byref(n)), "lbm_kernel_time")
+        return ms.value, n.value
+
+    def layout(self):
+        p = C.c_int64()
+        b = C.c_int64()
+        check(load().lbm_layout(self.ctx, C.byref(p), C.byref(b)), "lbm_layout")
+        return p.value, b.value
