@@ -170,6 +170,80 @@ int lbm_kernel_time(lbm_ctx* ctx, double* ms, int64_t* launches);
    multiple of 64) and bytes of one population buffer. */
 int lbm_layout(const lbm_ctx* ctx, int64_t* pitch, int64_t* buffer_bytes);
 
+/* ------------------------------------------------------------------------
+ * Entropic quasiequilibrium with the energy row, f*_M (Sec. 2: the
+ * maximiser of S(f) = -sum_i f_i ln(f_i / W_i) (Sec. 3.3) under
+ * m(f) = M = (rho, rho u1, rho u2, 2E); Sec. 3.3: ln f*_i = sum_j mu_j m_ji).
+ * D2Q9 rows m_i = (1, vx_i, vy_i, |v_i|^2), so f*_i = exp(mu . m_i) with the
+ * weights absorbed into mu.  Per site: Newton on the four multipliers, FP32
+ * iterations then FP64 iterations until max_j |m_j(f*) - M_j| / rho <= tol
+ * (default 1e-10); sites that miss it are re-solved by FP64 damped Newton
+ * from the isothermal rest start.  M outside the realisable set
+ * (2E/rho not in (|u1| + |u2|, 2), or rho <= 0) is reported as infeasible and
+ * receives the mass-momentum closed form of Sec. 4.2.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_fstar lbm_fstar; /* opaque solver workspace (device scratch) */
+
+typedef struct lbm_solve_stats {
+  int64_t n;             /* sites solved                                        */
+  int64_t n_infeasible;  /* M outside the realisable set                        */
+  int64_t n_fallback;    /* sites re-solved by the damped FP64 Newton           */
+  int64_t n_failed;      /* sites above tol after the fallback                  */
+  int64_t iter_hist[16]; /* first-pass Newton updates (FP32 + FP64) per feasible
+                            site; the last bin counts 15 or more                */
+  double mean_fp32_iters, mean_fp64_iters; /* per feasible site, first pass    */
+  double max_resid;      /* largest final residual of a converged site          */
+} lbm_solve_stats;
+
+/* Workspace for up to max_n sites, bound to a HIP stream. */
+int lbm_fstar_create(int64_t max_n, void* stream, lbm_fstar** out);
+/* Residual target tol (FP64), FP32-phase target tol32, iteration budgets. */
+int lbm_fstar_set_tolerance(lbm_fstar* s, double tol, double tol32, int32_t max32, int32_t max64);
+/*
+ * Solves n sites.  M: device double [4][n] (rho, rho u1, rho u2, 2E);
+ * mu: device double [4][n] output; start: LBM_START_DEFAULT (isothermal
+ * rest state at the site density), LBM_START_CLOSED_FORM (mass-momentum
+ * closed form of Sec. 4.2) or LBM_START_MLP (network net); iters, status:
+ * optional device uint8 [n] (Newton updates; 0 ok, 1 fallback ok,
+ * 2 infeasible, 3 failed).  stats (host, optional) synchronises the stream
+ * and returns LBM_E_NOCONV if any site failed; without stats the call is
+ * asynchronous.
+ */
+int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_t start,
+                    const lbm_mlp* net, uint8_t* iters, uint8_t* status, lbm_solve_stats* stats);
+void lbm_fstar_free(lbm_fstar* s);
+
+/* ------------------------------------------------------------------------
+ * Learned Newton warm start: MLP 4 -> 64 -> 64 -> 4, SiLU, BF16 matrix-core
+ * products with FP32 accumulation, FP32 master weights and Adam moments.
+ * Parameters (4740 floats): W1 [64][4], b1 [64], W2 [64][64], b2 [64],
+ * W3 [4][64], b3 [4].  Features of a site: (u1, u2, 2E/rho, |u|^2),
+ * x_k = (feature_k - in_shift_k) * in_scale_k; targets
+ * (mu0 - ln rho, mu1, mu2, mu3), y_k = (target_k - out_shift_k) * out_scale_k.
+ * ------------------------------------------------------------------------ */
+/* Kaiming-uniform weights from SplitMix64(seed), zero biases, identity norm. */
+int lbm_mlp_create(uint64_t seed, lbm_mlp** out);
+int lbm_mlp_get_params(const lbm_mlp* net, float* host_params);
+/* sets the weights (host float [4740]) and clears the Adam state */
+int lbm_mlp_set_params(lbm_mlp* net, const float* host_params);
+/* host float [16]: in_shift[4], in_scale[4], out_shift[4], out_scale[4] */
+int lbm_mlp_set_norm(lbm_mlp* net, const float* norm16);
+int lbm_mlp_get_norm(const lbm_mlp* net, float* norm16);
+/* Y = net(X) for normalised features; X, Y device float [n][4] */
+int lbm_mlp_forward(const lbm_mlp* net, const float* X, int64_t n, float* Y, void* stream);
+/* gradient of L = (1/(4n)) sum (net(X) - T)^2 into device float grad[4740];
+   loss (device float, optional) receives L; fixed-order (deterministic) */
+int lbm_mlp_loss_grad(lbm_mlp* net, const float* X, const float* T, int64_t n, float* grad,
+                      float* loss, void* stream);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) */
+int lbm_mlp_adam_step(lbm_mlp* net, const float* grad, double lr, void* stream);
+/* epochs of shuffled minibatch Adam over n samples (X, T device [n][4]);
+   loss_per_epoch (host float [epochs], optional): mean batch loss */
+int lbm_mlp_train(lbm_mlp* net, const float* X, const float* T, int64_t n, int32_t epochs,
+                  int32_t batch, double lr, uint64_t shuffle_seed, float* loss_per_epoch,
+                  void* stream);
+void lbm_mlp_free(lbm_mlp* net);
+
 /* sizeof(lbm_config) and sizeof(lbm_es_stats) as compiled into the
    library, so that bindings can check their struct layouts (host only). */
 void lbm_struct_sizes(int64_t* config_size, int64_t* stats_size);

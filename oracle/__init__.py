@@ -260,3 +260,36 @@ def adam_step(p, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """In-place Adam update of float64 arrays p, m, v."""
     lib().or_adam_step(_p(p), _p(m), _p(v), _p(np.ascontiguousarray(g, np.float64)), p.size, t,
                        lr, b1, b2, eps)
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start of the f*_M solve: features, targets, network start
+# ---------------------------------------------------------------------------
+
+def mlp_features(M, norm16) -> np.ndarray:
+    """Normalised network inputs of moment vectors M [4][n]: the features
+    (u1, u2, 2E/rho, |u|^2) shifted and scaled by norm16[0:4], norm16[4:8];
+    rounded to FP32 as the network receives them."""
+    M = np.asarray(M, np.float64)
+    nm = np.asarray(norm16, np.float32).astype(np.float64)
+    u1, u2, e = M[1] / M[0], M[2] / M[0], M[3] / M[0]
+    feat = np.stack([u1, u2, e, u1 * u1 + u2 * u2], axis=1)
+    return ((feat - nm[0:4]) * nm[4:8]).astype(np.float32).astype(np.float64)
+
+
+def mlp_targets(M, mu, norm16) -> np.ndarray:
+    """Normalised network targets of multipliers mu [4][n]:
+    (mu0 - ln rho, mu1, mu2, mu3) shifted and scaled by norm16[8:12], [12:16]."""
+    M = np.asarray(M, np.float64)
+    mu = np.asarray(mu, np.float64)
+    nm = np.asarray(norm16, np.float32).astype(np.float64)
+    tgt = np.stack([mu[0] - np.log(M[0]), mu[1], mu[2], mu[3]], axis=1)
+    return (tgt - nm[8:12]) * nm[12:16]
+
+
+def mlp_warm_start(params, norm16, M) -> np.ndarray:
+    """Network start (mu0 - ln rho, mu1, mu2, mu3) [4][n] for moments M, with
+    the BF16 rounding points of the GPU kernels emulated."""
+    nm = np.asarray(norm16, np.float32).astype(np.float64)
+    y = mlp_forward(params, mlp_features(M, norm16), bf16=True)
+    return (y / nm[12:16] + nm[8:12]).T.copy()

@@ -29,6 +29,15 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+// shared with the f*_M / MLP entry points (lbm_api_learn.hip)
+int lbm_internal_fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
@@ -122,7 +131,6 @@ int lbm_validate_config(const lbm_config* c) {
   if (!(c->nu >= 0.0)) return fail(LBM_E_INVAL, "nu must be >= 0 (got %g)", c->nu);
   if (!(c->delta >= 0.0)) return fail(LBM_E_INVAL, "delta must be >= 0 or +inf (got %g)", c->delta);
   if (c->k < 0) return fail(LBM_E_INVAL, "k must be >= 0 (got %d)", c->k);
-  if (c->k > 0 && (int64_t)c->k > c->nx * c->ny) return fail(LBM_E_INVAL, "k exceeds the number of sites");
   for (int s = 0; s < 4; ++s) {
     const int b = c->bc[s];
     const bool ok = s < 2 ? (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_INLET_EQ)
@@ -253,7 +261,8 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   g.beta2 = 2.0 / (1.0 + 6.0 * cfg->nu);
   g.delta = cfg->delta;
   g.ds_on = std::isinf(cfg->delta) ? 0 : 1;
-  g.kmax = cfg->k;
+  // at most N sites can be selected: "fewer than k: all of them"
+  g.kmax = (int32_t)std::min<int64_t>(cfg->k, c->N);
   // FP32 screen threshold delta (1 - 1e-2) - 64 eps32 sqrt(delta rho)
   const double dclamp = std::min(cfg->delta, 3.0e38);
   a.thr_a = (float)(0.99 * dclamp);
@@ -266,7 +275,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
 
   const size_t bytes = (size_t)Q * (size_t)c->plane * c->elem;
   const size_t ncap = (size_t)c->N;
-  const size_t kcap = (size_t)std::max(cfg->k, 1);
+  const size_t kcap = (size_t)std::max<int64_t>(g.kmax, 1);
 #define ALLOC(ptr, nbytes)                                                              \
   do {                                                                                \
     if (hipMalloc((void**)&(ptr), (nbytes)) != hipSuccess) {                          \

@@ -1,0 +1,315 @@
+// lbm_fstar.hip -- entropic quasiequilibrium f*_M with the energy row
+// (Sec. 2: f*_M = argmax{S(f) : m(f) = M}, M = (rho, rho u1, rho u2, 2E);
+// Sec. 3.3: ln f*_i is linear in the moment rows with Lagrange multipliers).
+//
+// Per site, Newton's method on the convex dual phi(mu) = sum_i exp(mu.m_i) -
+// mu.M in the multiplicative variables (A, X, Y, Z) = exp(mu).  On D2Q9,
+// |v|^2 = vx^2 + vy^2, so f*_i = A g(vx) g(vy) with g(0) = 1,
+// g(+-1) = Z X^{+-1} (Y for the y factor): every sum of the gradient and
+// Hessian follows from n = 1 + Z(X + 1/X), p = Z(X - 1/X), q = Z(X + 1/X)
+// per direction, with no per-population loop and no transcendental.
+//
+// Phases: FP32 Newton from the chosen start until the rho-relative residual
+// is ~1e-6; FP64 Newton (exp of small steps by its Taylor polynomial) until
+// max_j |m_j(f*) - M_j| / rho <= tol (1e-10); sites still above tol are
+// compacted and re-solved by FP64 damped Newton (Armijo backtracking) from
+// the isothermal rest start.  Infeasible M (2E/rho outside
+// (|u1| + |u2|, 2)) get the mass-momentum closed form of Sec. 4.2.
+#include <hip/hip_runtime.h>
+
+#include "lbm_fstar.hpp"
+
+namespace lbm {
+
+template <typename T> struct FS {
+  T a, X, Y, Z;  // a = A / rho
+};
+
+// gradient g = m(f)/rho - M/rho and Hessian (upper triangle, row-major
+// 00 01 02 03 11 12 13 22 23 33) of the dual, scaled by 1/rho
+template <typename T>
+__device__ __forceinline__ void fsys(const FS<T>& s, T u1, T u2, T e, T* g, T* H) {
+  T ix, iy;
+  if constexpr (sizeof(T) == 4) { ix = __builtin_amdgcn_rcpf(s.X); iy = __builtin_amdgcn_rcpf(s.Y); }
+  else { ix = T(1) / s.X; iy = T(1) / s.Y; }
+  const T qx = s.Z * (s.X + ix), px = s.Z * (s.X - ix), nx = T(1) + qx;
+  const T qy = s.Z * (s.Y + iy), py = s.Z * (s.Y - iy), ny = T(1) + qy;
+  const T a = s.a;
+  const T r = a * nx * ny, jx = a * px * ny, jy = a * nx * py;
+  const T ee = a * (qx * ny + nx * qy);
+  g[0] = r - T(1);
+  g[1] = jx - u1;
+  g[2] = jy - u2;
+  g[3] = ee - e;
+  H[0] = r;
+  H[1] = jx;
+  H[2] = jy;
+  H[3] = ee;
+  H[4] = a * qx * ny;
+  H[5] = a * px * py;
+  H[6] = a * px * (ny + qy);
+  H[7] = a * nx * qy;
+  H[8] = a * py * (nx + qx);
+  H[9] = a * (qx * ny + T(2) * qx * qy + nx * qy);
+}
+
+template <typename T> __device__ __forceinline__ T recip(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);
+  else return T(1) / x;
+}
+
+// solve H d = -g (H symmetric positive definite) by LDL^T
+template <typename T>
+__device__ __forceinline__ void fsolve(const T* H, const T* g, T* d) {
+  const T D0 = H[0], i0 = recip(D0);
+  const T l10 = H[1] * i0, l20 = H[2] * i0, l30 = H[3] * i0;
+  const T D1 = H[4] - l10 * H[1], i1 = recip(D1);
+  const T l21 = (H[5] - l20 * H[1]) * i1, l31 = (H[6] - l30 * H[1]) * i1;
+  const T D2 = H[7] - l20 * H[2] - l21 * l21 * D1, i2 = recip(D2);
+  const T l32 = (H[8] - l30 * H[2] - l31 * l21 * D1) * i2;
+  const T D3 = H[9] - l30 * H[3] - l31 * l31 * D1 - l32 * l32 * D2, i3 = recip(D3);
+  // L y = -g
+  const T y0 = -g[0];
+  const T y1 = -g[1] - l10 * y0;
+  const T y2 = -g[2] - l20 * y0 - l21 * y1;
+  const T y3 = -g[3] - l30 * y0 - l31 * y1 - l32 * y2;
+  // D L^T d = y
+  d[3] = y3 * i3;
+  d[2] = y2 * i2 - l32 * d[3];
+  d[1] = y1 * i1 - l21 * d[2] - l31 * d[3];
+  d[0] = y0 * i0 - l10 * d[1] - l20 * d[2] - l30 * d[3];
+}
+
+template <typename T> __device__ __forceinline__ T resid(const T* g) {
+  T r = __builtin_fabs(g[0]);
+  r = fmax(r, (T)__builtin_fabs(g[1]));
+  r = fmax(r, (T)__builtin_fabs(g[2]));
+  r = fmax(r, (T)__builtin_fabs(g[3]));
+  return r;
+}
+
+// exp(d) for the FP64 phase: Taylor polynomial when |d| < 1e-3 (truncation
+// d^5/120 < 1e-17), the library exp otherwise
+__device__ __forceinline__ double exp_step(double d) {
+  if (__builtin_fabs(d) < 1e-3)
+    return 1.0 + d * (1.0 + 0.5 * d * (1.0 + (1.0 / 3.0) * d * (1.0 + 0.25 * d)));
+  return ::exp(d);
+}
+
+__device__ __forceinline__ bool feasible(double rho, double u1, double u2, double e) {
+  return rho > 0.0 && e > __builtin_fabs(u1) + __builtin_fabs(u2) && e < 2.0;
+}
+
+// closed-form mass-momentum start (Sec. 4.2): Z = 1/4,
+// X = (2u + sqrt(1 + 3u^2)) / (1 - u), a = (4/9)(2 - s_x)(2 - s_y)
+template <typename T>
+__device__ __forceinline__ FS<T> closed_form(T u1, T u2) {
+  const T sx = sqrt(T(1) + T(3) * u1 * u1), sy = sqrt(T(1) + T(3) * u2 * u2);
+  FS<T> s;
+  s.a = T(4.0 / 9.0) * (T(2) - sx) * (T(2) - sy);
+  s.X = (T(2) * u1 + sx) / (T(1) - u1);
+  s.Y = (T(2) * u2 + sy) / (T(1) - u2);
+  s.Z = T(0.25);
+  return s;
+}
+
+// FP64 damped Newton from the rest start; returns iterations (negative on failure)
+__device__ int newton64_damped(double u1, double u2, double e, double tol, int max_it, FS<double>& s,
+                               double& res) {
+  s.a = 4.0 / 9.0;
+  s.X = 1.0;
+  s.Y = 1.0;
+  s.Z = 0.25;
+  double g[4], H[10], d[4];
+  for (int it = 0; it <= max_it; ++it) {
+    fsys<double>(s, u1, u2, e, g, H);
+    res = resid(g);
+    if (res <= tol) return it;
+    if (it == max_it) break;
+    fsolve<double>(H, g, d);
+    double t = 1.0;
+    if (res > 1e-3) {
+      // Armijo on phi/rho = a n_x n_y - (ln a, ln X, ln Y, ln Z) . (1, u1, u2, e)
+      const double phi0 = H[0] - (::log(s.a) + ::log(s.X) * u1 + ::log(s.Y) * u2 + ::log(s.Z) * e);
+      const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2] + g[3] * d[3];
+      for (int ls = 0; ls < 60; ++ls) {
+        FS<double> q;
+        q.a = s.a * ::exp(t * d[0]);
+        q.X = s.X * ::exp(t * d[1]);
+        q.Y = s.Y * ::exp(t * d[2]);
+        q.Z = s.Z * ::exp(t * d[3]);
+        double gq[4], Hq[10];
+        fsys<double>(q, u1, u2, e, gq, Hq);
+        const double phi = Hq[0] - (::log(q.a) + ::log(q.X) * u1 + ::log(q.Y) * u2 + ::log(q.Z) * e);
+        if (phi <= phi0 + 1e-4 * t * slope) break;
+        t *= 0.5;
+      }
+    }
+    s.a *= ::exp(t * d[0]);
+    s.X *= ::exp(t * d[1]);
+    s.Y *= ::exp(t * d[2]);
+    s.Z *= ::exp(t * d[3]);
+  }
+  return -1;
+}
+
+__device__ __forceinline__ void write_mu(double* mu, int64_t n, int64_t i, double rho, const FS<double>& s) {
+  mu[i] = ::log(s.a * rho);
+  mu[n + i] = ::log(s.X);
+  mu[2 * n + i] = ::log(s.Y);
+  mu[3 * n + i] = ::log(s.Z);
+}
+
+// block-aggregated statistics
+struct SolveAcc {
+  uint32_t hist[16];
+  uint32_t sum32, sum64, infeasible, fail;
+  unsigned long long maxres_bits;
+};
+
+__device__ __forceinline__ void acc_add(SolveAcc* sh, int it32, int it64, bool infeas, bool fail, double res) {
+  const int tot = it32 + it64;
+  atomicAdd(&sh->hist[tot < 15 ? tot : 15], 1u);
+  atomicAdd(&sh->sum32, (uint32_t)it32);
+  atomicAdd(&sh->sum64, (uint32_t)it64);
+  if (infeas) atomicAdd(&sh->infeasible, 1u);
+  if (fail) atomicAdd(&sh->fail, 1u);
+  if (!infeas && !fail) atomicMax(&sh->maxres_bits, (unsigned long long)__double_as_longlong(res));
+}
+
+template <int START>
+__global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
+  __shared__ SolveAcc sh;
+  if (threadIdx.x < sizeof(SolveAcc) / 4) ((uint32_t*)&sh)[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = a.n;
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < n) {
+    const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
+    int it32 = 0, it64 = 0;
+    bool infeas = false, fail = false;
+    double res = 0.0;
+    if (!feasible(rho, u1, u2, e)) {
+      infeas = true;
+      if (__builtin_fabs(u1) < 1.0 && __builtin_fabs(u2) < 1.0 && rho > 0.0) {
+        write_mu(a.mu, n, i, rho, closed_form<double>(u1, u2));
+      } else {
+        for (int c = 0; c < 4; ++c) a.mu[c * n + i] = __builtin_nan("");
+      }
+      if (a.status) a.status[i] = 2;
+    } else {
+      // ---- FP32 phase
+      FS<float> s;
+      if (START == START_CLOSED) {
+        s = closed_form<float>((float)u1, (float)u2);
+      } else if (START == START_WARM) {
+        s.a = __expf(a.warm[i]);
+        s.X = __expf(a.warm[n + i]);
+        s.Y = __expf(a.warm[2 * n + i]);
+        s.Z = __expf(a.warm[3 * n + i]);
+      } else {
+        s.a = 4.0f / 9.0f;
+        s.X = 1.0f;
+        s.Y = 1.0f;
+        s.Z = 0.25f;
+      }
+      const float fu1 = (float)u1, fu2 = (float)u2, fe = (float)e;
+      float g[4], H[10], d[4];
+      float prev = 3.0e38f;
+      for (;;) {
+        fsys<float>(s, fu1, fu2, fe, g, H);
+        const float r = resid(g);
+        if (!(r > a.tol32) || it32 >= a.max32 || !(r < 0.25f * prev)) break;
+        prev = r;
+        fsolve<float>(H, g, d);
+        float dm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
+        const float sc = dm > 1.0f ? 1.0f / dm : 1.0f;
+        s.a *= __expf(sc * d[0]);
+        s.X *= __expf(sc * d[1]);
+        s.Y *= __expf(sc * d[2]);
+        s.Z *= __expf(sc * d[3]);
+        ++it32;
+      }
+      // ---- FP64 phase
+      FS<double> t{(double)s.a, (double)s.X, (double)s.Y, (double)s.Z};
+      bool ok = false;
+      if (__builtin_isfinite(t.a) && t.a > 0.0 && t.X > 0.0 && t.Y > 0.0 && t.Z > 0.0 &&
+          __builtin_isfinite(t.X) && __builtin_isfinite(t.Y) && __builtin_isfinite(t.Z)) {
+        double gd[4], Hd[10], dd[4];
+        for (;;) {
+          fsys<double>(t, u1, u2, e, gd, Hd);
+          res = resid(gd);
+          if (res <= a.tol) { ok = true; break; }
+          if (it64 >= a.max64 || !(res < 1e-2)) break;
+          fsolve<double>(Hd, gd, dd);
+          t.a *= exp_step(dd[0]);
+          t.X *= exp_step(dd[1]);
+          t.Y *= exp_step(dd[2]);
+          t.Z *= exp_step(dd[3]);
+          ++it64;
+        }
+      }
+      if (ok) {
+        write_mu(a.mu, n, i, rho, t);
+        if (a.status) a.status[i] = 0;
+      } else {
+        fail = true;
+        const uint32_t slot = atomicAdd(&a.ctr[0], 1u);
+        a.fail_list[slot] = (uint32_t)i;
+      }
+    }
+    if (a.iters) a.iters[i] = (uint8_t)(it32 + it64 < 255 ? it32 + it64 : 255);
+    acc_add(&sh, it32, it64, infeas, fail, res);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16 && sh.hist[threadIdx.x]) atomicAdd(&a.stats->hist[threadIdx.x], (unsigned long long)sh.hist[threadIdx.x]);
+  if (threadIdx.x == 16) {
+    atomicAdd(&a.stats->sum32, (unsigned long long)sh.sum32);
+    atomicAdd(&a.stats->sum64, (unsigned long long)sh.sum64);
+    atomicAdd(&a.stats->infeasible, (unsigned long long)sh.infeasible);
+    atomicMax(&a.stats->maxres_bits, sh.maxres_bits);
+  }
+}
+
+// FP64 damped-Newton fallback over the compacted failures
+__global__ __launch_bounds__(64) void k_fstar_fallback(FstarArgs a) {
+  const uint32_t nf = a.ctr[0];
+  const int64_t n = a.n;
+  for (uint32_t t = blockIdx.x * 64u + threadIdx.x; t < nf; t += gridDim.x * 64u) {
+    const int64_t i = a.fail_list[t];
+    const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
+    FS<double> s;
+    double res = 0.0;
+    const int it = newton64_damped(u1, u2, e, a.tol, 200, s, res);
+    write_mu(a.mu, n, i, rho, s);
+    if (a.status) a.status[i] = it >= 0 ? 1 : 3;
+    atomicAdd(&a.stats->fallback, 1ull);
+    if (it < 0) atomicAdd(&a.stats->failed, 1ull);
+    else atomicMax(&a.stats->maxres_bits, (unsigned long long)__double_as_longlong(res));
+  }
+}
+
+__global__ void k_fstar_clear(FstarArgs a) {
+  const int t = threadIdx.x;
+  if (t < 4) a.ctr[t] = 0;
+  if (t < 16) a.stats->hist[t] = 0;
+  if (t == 0) {
+    a.stats->sum32 = a.stats->sum64 = a.stats->infeasible = 0;
+    a.stats->fallback = a.stats->failed = 0;
+    a.stats->maxres_bits = 0;
+  }
+}
+
+hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s) {
+  hipLaunchKernelGGL(k_fstar_clear, dim3(1), dim3(64), 0, s, a);
+  const unsigned nb = (unsigned)((a.n + 255) / 256);
+  if (nb > 0) {
+    if (start == START_CLOSED) hipLaunchKernelGGL((k_fstar<START_CLOSED>), dim3(nb), dim3(256), 0, s, a);
+    else if (start == START_WARM) hipLaunchKernelGGL((k_fstar<START_WARM>), dim3(nb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_fstar<START_REST>), dim3(nb), dim3(256), 0, s, a);
+  }
+  hipLaunchKernelGGL(k_fstar_fallback, dim3(64), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,64 @@
+// lbm_fstar.hpp -- launch interface of the f*_M solver and the MLP kernels
+// (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum : int { START_REST = 0, START_CLOSED = 1, START_WARM = 2 };
+
+struct FstarStats {
+  unsigned long long hist[16];   // Newton updates per site (FP32 + FP64 phases)
+  unsigned long long sum32, sum64, infeasible, fallback, failed;
+  unsigned long long maxres_bits; // bits of the largest final residual (non-negative double)
+};
+
+struct FstarArgs {
+  const double* M;      // [4][n]
+  int64_t n;
+  double* mu;           // [4][n]
+  const float* warm;    // [4][n]: (mu0 - ln rho, mu1, mu2, mu3) start, START_WARM only
+  uint8_t* iters;       // [n] or null
+  uint8_t* status;      // [n] or null: 0 ok, 1 fallback ok, 2 infeasible, 3 failed
+  uint32_t* ctr;        // [4]: ctr[0] = number of failures of the first pass
+  uint32_t* fail_list;  // [n]
+  FstarStats* stats;
+  double tol;           // FP64 residual target
+  float tol32;          // FP32 phase target
+  int max32, max64;     // iteration budgets of the two phases
+};
+
+hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// MLP 4 -> 64 -> 64 -> 4 (SiLU), BF16 MFMA with FP32 accumulation
+// ---------------------------------------------------------------------------
+constexpr int MLP_NPARAM = 4740;
+constexpr int MLP_OW1 = 0, MLP_OB1 = 256, MLP_OW2 = 320, MLP_OB2 = 4416, MLP_OW3 = 4480, MLP_OB3 = 4736;
+
+struct MlpNorm {
+  float in_shift[4], in_scale[4];    // x_k = (feature_k - shift) * scale
+  float out_shift[4], out_scale[4];  // target_k = y_k / scale + shift
+};
+
+// forward of n samples X[n][4] (normalised features) -> Y[n][4]
+hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n, float* Y, hipStream_t s);
+// warm start for the f*_M solver: features of M, forward, de-normalised
+// (mu0 - ln rho, mu1, mu2, mu3) into warm[4][n]
+hipError_t launch_mlp_warm(const float* params, const MlpNorm& nm, const double* M, int64_t n, float* warm,
+                           hipStream_t s);
+// per-block gradient partials of the MSE loss over n samples; returns the
+// number of blocks used (partials is [nblocks][MLP_NPARAM + 1], the last
+// column the block's loss sum)
+int mlp_grad_blocks(int64_t n);
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* T, int64_t n, const int32_t* idx,
+                           float* partials, hipStream_t s);
+// reduce partials (fixed order), Adam update of params (FP32 master), m, v
+hipError_t launch_mlp_reduce(const float* partials, int nblocks, int64_t n, float* grad, float* loss,
+                             hipStream_t s);
+hipError_t launch_adam(float* params, float* m, float* v, const float* grad, int64_t t, float lr, float b1,
+                       float b2, float eps, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,519 @@
+// lbm_mlp.hip -- the learned warm start of the f*_M solve: an MLP
+// 4 -> 64 -> 64 -> 4 with SiLU, BF16 operands on the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; forward, backward
+// (per-block gradient partials, fixed-order reduction) and Adam.
+//
+// Products are formed transposed, out^T = W . act^T, so that the weights are
+// the A operand (held in registers for a whole kernel) and a tile of 16
+// samples is the B operand.  With lane l, r = l % 16, g = l / 16:
+//   A operand: lane holds A[r][8g .. 8g+7]      (16 x 32, row-major K)
+//   B operand: lane holds B[8g .. 8g+7][r]      (32 x 16)
+//   D result : lane holds D[4g .. 4g+3][r]      (16 x 16)
+// Activations move between layers through per-wave LDS tiles.
+//
+// BF16 rounding points (the CPU oracle's emulation follows them): inputs,
+// weights, hidden activations after SiLU, and back-propagated deltas where
+// they enter a product; biases, bias gradients and SiLU are FP32.
+#include <hip/hip_runtime.h>
+
+#include "lbm_fstar.hpp"
+
+namespace lbm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+  bf16x8 v;
+  #pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+  return v;
+}
+
+__device__ __forceinline__ bf16x8 load8(const float* p) {
+  bf16x8 v;
+  #pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (__bf16)p[j];
+  return v;
+}
+
+// weight operands of the three layers for this lane
+struct Weights {
+  bf16x8 w1[4];     // layer 1, unit tile t: W1[16t + r][k], k < 4 real
+  bf16x8 w2[4][2];  // layer 2, unit tile t, k step kk: W2[16t + r][32kk + 8g + j]
+  bf16x8 w3[2];     // layer 3, k step kk: W3[r][32kk + 8g + j], r < 4 real
+  float b1[4][4], b2[4][4];  // bias of unit 16t + 4g + j
+  float b3[4];               // bias of output j (lanes g == 0)
+};
+
+__device__ void load_weights(const float* __restrict__ p, int r, int g, Weights& w) {
+  #pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    bf16x8 v = zero8();
+    if (g == 0) {
+      #pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = (__bf16)p[MLP_OW1 + (16 * t + r) * 4 + j];
+    }
+    w.w1[t] = v;
+    #pragma unroll
+    for (int kk = 0; kk < 2; ++kk) w.w2[t][kk] = load8(p + MLP_OW2 + (16 * t + r) * 64 + 32 * kk + 8 * g);
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      w.b1[t][j] = p[MLP_OB1 + 16 * t + 4 * g + j];
+      w.b2[t][j] = p[MLP_OB2 + 16 * t + 4 * g + j];
+    }
+  }
+  #pragma unroll
+  for (int kk = 0; kk < 2; ++kk) w.w3[kk] = r < 4 ? load8(p + MLP_OW3 + r * 64 + 32 * kk + 8 * g) : zero8();
+  #pragma unroll
+  for (int j = 0; j < 4; ++j) w.b3[j] = g == 0 ? p[MLP_OB3 + j] : 0.0f;
+}
+
+// LDS row strides (bf16 elements): site-major rows of 64 units, unit-major
+// rows of 32 samples; padded against bank conflicts
+constexpr int SROW = 72;
+constexpr int TROW = 40;
+
+// forward of one tile of 16 samples.  xin: B operand of layer 1 (lanes g == 0
+// hold the 4 BF16 features of sample r).  Hs1/Hs2: this wave's site-major
+// LDS tiles [16][SROW].  z1/z2 (optional) receive the pre-activations in the
+// D layout; y receives the output (lanes g == 0, outputs 0..3 of sample r).
+template <bool KEEP>
+__device__ __forceinline__ void forward16(const Weights& w, bf16x8 xin, __bf16* Hs1, __bf16* Hs2, int r, int g,
+                                          f32x4* z1, f32x4* z2, f32x4& y) {
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  #pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 d = mfma(w.w1[t], xin, zero);
+    bf16x4 h;
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float z = d[j] + w.b1[t][j];
+      if (KEEP) z1[t][j] = z;
+      h[j] = (__bf16)silu(z);
+    }
+    *(bf16x4*)(Hs1 + r * SROW + 16 * t + 4 * g) = h;
+  }
+  __syncthreads();
+  bf16x8 b2[2];
+  #pragma unroll
+  for (int kk = 0; kk < 2; ++kk) b2[kk] = *(const bf16x8*)(Hs1 + r * SROW + 32 * kk + 8 * g);
+  #pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 d = mfma(w.w2[t][0], b2[0], zero);
+    d = mfma(w.w2[t][1], b2[1], d);
+    bf16x4 h;
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float z = d[j] + w.b2[t][j];
+      if (KEEP) z2[t][j] = z;
+      h[j] = (__bf16)silu(z);
+    }
+    *(bf16x4*)(Hs2 + r * SROW + 16 * t + 4 * g) = h;
+  }
+  __syncthreads();
+  bf16x8 b3[2];
+  #pragma unroll
+  for (int kk = 0; kk < 2; ++kk) b3[kk] = *(const bf16x8*)(Hs2 + r * SROW + 32 * kk + 8 * g);
+  f32x4 d = mfma(w.w3[0], b3[0], zero);
+  d = mfma(w.w3[1], b3[1], d);
+  #pragma unroll
+  for (int j = 0; j < 4; ++j) y[j] = d[j] + w.b3[j];
+}
+
+// ---------------------------------------------------------------------------
+// inference
+// ---------------------------------------------------------------------------
+// Each wave takes tiles of 16 samples; the block's 4 waves step through
+// their tiles in lock step so that block barriers can order the LDS traffic.
+template <bool WARM>
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ params, const float* __restrict__ X,
+                                                     const double* __restrict__ M, MlpNorm nm, int64_t n,
+                                                     float* __restrict__ out) {
+  __shared__ __bf16 lds[4][2][16 * SROW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  Weights w;
+  load_weights(params, r, g, w);
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t base = blockIdx.x * 4ll; base < ntiles; base += stride) {
+    const int64_t tile = base + wv;
+    const int64_t s = tile * 16 + r;
+    const bool live = tile < ntiles && s < n;
+    bf16x8 xin = zero8();
+    double rho = 1.0;
+    if (g == 0 && live) {
+      float f[4];
+      if (WARM) {
+        rho = M[s];
+        const double u1 = M[n + s] / rho, u2 = M[2 * n + s] / rho, e = M[3 * n + s] / rho;
+        const double feat[4] = {u1, u2, e, u1 * u1 + u2 * u2};
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) f[k] = (float)((feat[k] - nm.in_shift[k]) * nm.in_scale[k]);
+      } else {
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) f[k] = X[s * 4 + k];
+      }
+      #pragma unroll
+      for (int k = 0; k < 4; ++k) xin[k] = (__bf16)f[k];
+    }
+    f32x4 y;
+    forward16<false>(w, xin, lds[wv][0], lds[wv][1], r, g, nullptr, nullptr, y);
+    if (g == 0 && live) {
+      if (WARM) {
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) out[k * n + s] = y[k] / nm.out_scale[k] + nm.out_shift[k];
+      } else {
+        *(f32x4*)(out + s * 4) = y;
+      }
+    }
+    __syncthreads();  // LDS tiles are reused by the next iteration
+  }
+}
+
+static unsigned fwd_grid(int64_t n) {
+  const int64_t tiles = (n + 15) / 16;
+  int64_t nb = (tiles + 3) / 4;
+  return (unsigned)(nb < 2048 ? (nb > 0 ? nb : 1) : 2048);
+}
+
+hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n, float* Y, hipStream_t s) {
+  MlpNorm nm{};
+  hipLaunchKernelGGL((k_mlp_forward<false>), dim3(fwd_grid(n)), dim3(256), 0, s, params, X, nullptr, nm, n, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_warm(const float* params, const MlpNorm& nm, const double* M, int64_t n, float* warm,
+                           hipStream_t s) {
+  hipLaunchKernelGGL((k_mlp_forward<true>), dim3(fwd_grid(n)), dim3(256), 0, s, params, nullptr, M, nm, n, warm);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gradient of the MSE loss L = (1/(4 n)) sum_s sum_o (y_so - t_so)^2
+// ---------------------------------------------------------------------------
+// Blocks of 2 waves; a wave takes chunks of 32 samples (two tiles of 16),
+// the K dimension of the weight-gradient products.  Per-wave LDS:
+struct GradLds {
+  __bf16 hs1[2][16 * SROW];  // site-major H1 of the two tiles (forward operand)
+  __bf16 hs2[2][16 * SROW];  // site-major H2; reused for site-major dZ2
+  __bf16 h1t[64 * TROW];     // unit-major H1 [unit][sample]
+  __bf16 h2t[64 * TROW];     // unit-major H2
+  __bf16 dz2t[64 * TROW];    // unit-major dZ2
+  __bf16 dz1t[64 * TROW];    // unit-major dZ1
+  __bf16 xt[16 * TROW];      // feature-major X [k][sample], k < 4 real
+  __bf16 gyt[16 * TROW];     // output-major dY [o][sample], o < 4 real
+  __bf16 gys[32 * 8];        // sample-major dY [sample][o], o < 4 real
+};
+
+constexpr int GRAD_WAVES = 1;
+
+__global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const float* __restrict__ params,
+                                                              const float* __restrict__ X,
+                                                              const float* __restrict__ T, int64_t n,
+                                                              const int32_t* __restrict__ idx,
+                                                              float* __restrict__ partials) {
+  // the per-wave tiles and the final reduction buffer share the LDS
+  constexpr size_t TILE_BYTES = sizeof(GradLds) * GRAD_WAVES;
+  constexpr size_t RED_BYTES = sizeof(float) * GRAD_WAVES * (MLP_NPARAM + 1);
+  __shared__ __attribute__((aligned(16))) char lds_raw[TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES];
+  GradLds* L = (GradLds*)lds_raw;
+  float(*red)[MLP_NPARAM + 1] = (float(*)[MLP_NPARAM + 1])lds_raw;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+  GradLds& S = L[wv];
+  Weights w;
+  load_weights(params, r, g, w);
+  // transposed weight operands for the backward products
+  bf16x8 w3t[4];     // A of dH2 = W3^T dY: W3^T[16t + r][o = 8g + j] (o < 4 real)
+  bf16x8 w2t[4][2];  // A of dH1 = W2^T dZ2: W2^T[16t + r][32kk + 8g + j] = W2[32kk+8g+j][16t+r]
+  #pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    bf16x8 v = zero8();
+    if (g == 0) {
+      #pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = (__bf16)params[MLP_OW3 + j * 64 + 16 * t + r];
+    }
+    w3t[t] = v;
+    #pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      bf16x8 u;
+      #pragma unroll
+      for (int j = 0; j < 8; ++j) u[j] = (__bf16)params[MLP_OW2 + (32 * kk + 8 * g + j) * 64 + 16 * t + r];
+      w2t[t][kk] = u;
+    }
+  }
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 gw1[4], gw2[4][4], gw3[4];  // weight-gradient tiles (D layout)
+  float gb1[4][4], gb2[4][4], gb3[4], lsum = 0.f;
+  #pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    gw1[t] = zero;
+    gw3[t] = zero;
+    #pragma unroll
+    for (int u = 0; u < 4; ++u) gw2[t][u] = zero;
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) { gb1[t][j] = 0.f; gb2[t][j] = 0.f; }
+    gb3[t] = 0.f;
+  }
+  const float gscale = 2.0f / (4.0f * (float)n);
+
+  const int64_t nchunks = (n + 31) / 32;
+  for (int64_t base = (int64_t)blockIdx.x * GRAD_WAVES; base < nchunks; base += (int64_t)gridDim.x * GRAD_WAVES) {
+    const int64_t chunk = base + wv;
+    f32x4 z1[2][4], z2[2][4], y[2];
+    float tgt[2][4];
+    bool live[2];
+    // ---- forward of the two tiles
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t s = chunk * 32 + h * 16 + r;
+      live[h] = chunk < nchunks && s < n;
+      bf16x8 xin = zero8();
+      const int sl = h * 16 + r;  // sample within the chunk
+      if (g == 0) {
+        float f[4] = {0.f, 0.f, 0.f, 0.f};
+        if (live[h]) {
+          const int64_t src = idx ? (int64_t)idx[s] : s;
+          #pragma unroll
+          for (int k = 0; k < 4; ++k) { f[k] = X[src * 4 + k]; tgt[h][k] = T[src * 4 + k]; }
+        }
+        #pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          xin[k] = (__bf16)f[k];
+          S.xt[k * TROW + sl] = xin[k];
+        }
+      }
+      forward16<true>(w, xin, S.hs1[h], S.hs2[h], r, g, z1[h], z2[h], y[h]);
+    }
+    // unit-major copies of H1 and H2 for the weight-gradient products
+    #pragma unroll
+    for (int h = 0; h < 2; ++h)
+      #pragma unroll
+      for (int t = 0; t < 4; ++t)
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = 16 * t + 4 * g + j;
+          S.h1t[u * TROW + h * 16 + r] = S.hs1[h][r * SROW + u];
+          S.h2t[u * TROW + h * 16 + r] = S.hs2[h][r * SROW + u];
+        }
+    // ---- output delta dY = 2 (y - t) / (4 n), FP32; BF16 copies for products
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int sl = h * 16 + r;
+      if (g == 0) {
+        #pragma unroll
+        for (int o = 0; o < 4; ++o) {
+          float gy = 0.f;
+          if (live[h]) {
+            const float d = y[h][o] - tgt[h][o];
+            lsum += d * d;
+            gy = gscale * d;
+          }
+          gb3[o] += gy;
+          const __bf16 gbf = (__bf16)gy;
+          S.gyt[o * TROW + sl] = gbf;
+          S.gys[sl * 8 + o] = gbf;
+        }
+        #pragma unroll
+        for (int o = 4; o < 8; ++o) S.gys[sl * 8 + o] = (__bf16)0.0f;
+      }
+    }
+    // zero rows 4..15 of the output-major dY and feature-major X (A/B padding)
+    for (int e = lane; e < 12 * 32; e += 64) {
+      S.gyt[(4 + e / 32) * TROW + (e & 31)] = (__bf16)0.0f;
+      S.xt[(4 + e / 32) * TROW + (e & 31)] = (__bf16)0.0f;
+    }
+    __syncthreads();
+    // ---- dW3 += dY^T-chunk . H2 : A = dY [o][32 samples], B = H2 [32 samples][16 units]
+    {
+      const bf16x8 a = *(const bf16x8*)(S.gyt + r * TROW + 8 * g);
+      #pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bf16x8 b = *(const bf16x8*)(S.h2t + (16 * t + r) * TROW + 8 * g);
+        gw3[t] = mfma(a, b, gw3[t]);
+      }
+    }
+    // ---- dZ2 = (W3^T dY) * silu'(z2), per tile of 16 samples
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf16x8 b = zero8();
+      if (g == 0) b = *(const bf16x8*)(S.gys + (h * 16 + r) * 8);
+      #pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const f32x4 dh = mfma(w3t[t], b, zero);
+        bf16x4 q;
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float dz = live[h] ? dh[j] * dsilu(z2[h][t][j]) : 0.f;
+          gb2[t][j] += dz;
+          q[j] = (__bf16)dz;
+          S.dz2t[(16 * t + 4 * g + j) * TROW + h * 16 + r] = q[j];
+        }
+        *(bf16x4*)(S.hs2[h] + r * SROW + 16 * t + 4 * g) = q;  // site-major dZ2
+      }
+    }
+    __syncthreads();
+    // ---- dW2 += dZ2 . H1 : A = dZ2 [16 units j][32 samples], B = H1 [32 samples][16 units k]
+    #pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      const bf16x8 a = *(const bf16x8*)(S.dz2t + (16 * tj + r) * TROW + 8 * g);
+      #pragma unroll
+      for (int tk = 0; tk < 4; ++tk) {
+        const bf16x8 b = *(const bf16x8*)(S.h1t + (16 * tk + r) * TROW + 8 * g);
+        gw2[tj][tk] = mfma(a, b, gw2[tj][tk]);
+      }
+    }
+    // ---- dZ1 = (W2^T dZ2) * silu'(z1)
+    #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf16x8 b[2];
+      #pragma unroll
+      for (int kk = 0; kk < 2; ++kk) b[kk] = *(const bf16x8*)(S.hs2[h] + r * SROW + 32 * kk + 8 * g);
+      #pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 dh = mfma(w2t[t][0], b[0], zero);
+        dh = mfma(w2t[t][1], b[1], dh);
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float dz = live[h] ? dh[j] * dsilu(z1[h][t][j]) : 0.f;
+          gb1[t][j] += dz;
+          S.dz1t[(16 * t + 4 * g + j) * TROW + h * 16 + r] = (__bf16)dz;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- dW1 += dZ1 . X : A = dZ1 [16 units][32 samples], B = X [32 samples][16 (4 real)]
+    {
+      const bf16x8 b = *(const bf16x8*)(S.xt + r * TROW + 8 * g);
+      #pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bf16x8 a = *(const bf16x8*)(S.dz1t + (16 * t + r) * TROW + 8 * g);
+        gw1[t] = mfma(a, b, gw1[t]);
+      }
+    }
+    __syncthreads();  // LDS is rewritten by the next chunk
+  }
+
+  // ---- per-wave results -> block partial (fixed order over waves)
+  __syncthreads();  // the tiles are dead; the LDS becomes the reduction buffer
+  for (int p = threadIdx.x; p < GRAD_WAVES * (MLP_NPARAM + 1); p += blockDim.x) (&red[0][0])[p] = 0.f;
+  __syncthreads();
+  float* R = red[wv];
+  // weight tiles: D layout, lane holds rows 4g + j, column r
+  #pragma unroll
+  for (int t = 0; t < 4; ++t)
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 16 * t + 4 * g + j;  // hidden unit of layer 1
+      if (r < 4) R[MLP_OW1 + row * 4 + r] = gw1[t][j];
+      #pragma unroll
+      for (int tk = 0; tk < 4; ++tk) R[MLP_OW2 + row * 64 + 16 * tk + r] = gw2[t][tk][j];
+    }
+  if (g == 0)
+    #pragma unroll
+    for (int t = 0; t < 4; ++t)
+      #pragma unroll
+      for (int j = 0; j < 4; ++j) R[MLP_OW3 + j * 64 + 16 * t + r] = gw3[t][j];
+  __syncthreads();
+  // biases: lanes with the same g share units; sum over r in a fixed order
+  #pragma unroll
+  for (int t = 0; t < 4; ++t)
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float a1 = gb1[t][j], a2 = gb2[t][j];
+      #pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        a1 += __shfl_xor(a1, off, 16);
+        a2 += __shfl_xor(a2, off, 16);
+      }
+      if (r == 0) {
+        R[MLP_OB1 + 16 * t + 4 * g + j] = a1;
+        R[MLP_OB2 + 16 * t + 4 * g + j] = a2;
+      }
+    }
+  #pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    float a3 = gb3[o];
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a3 += __shfl_xor(a3, off);
+    if (lane == 0) R[MLP_OB3 + o] = a3;
+  }
+  float ls = lsum;
+  #pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ls += __shfl_xor(ls, off);
+  if (lane == 0) R[MLP_NPARAM] = ls;
+  __syncthreads();
+  for (int p = threadIdx.x; p < MLP_NPARAM + 1; p += blockDim.x) {
+    float v = 0.f;
+    #pragma unroll
+    for (int q = 0; q < GRAD_WAVES; ++q) v += red[q][p];
+    partials[(int64_t)blockIdx.x * (MLP_NPARAM + 1) + p] = v;
+  }
+}
+
+int mlp_grad_blocks(int64_t n) {
+  const int64_t chunks = (n + 31) / 32;
+  int64_t nb = (chunks + GRAD_WAVES - 1) / GRAD_WAVES;
+  return (int)(nb < 256 ? (nb > 0 ? nb : 1) : 256);
+}
+
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* T, int64_t n, const int32_t* idx,
+                           float* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(mlp_grad_blocks(n)), dim3(64 * GRAD_WAVES), 0, s, params, X, T, n, idx,
+                     partials);
+  return hipGetLastError();
+}
+
+// fixed-order sum of the block partials: grad[p] and loss = sum / (4 n)
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ partials, int nblocks, int64_t n,
+                                                    float* __restrict__ grad, float* __restrict__ loss) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p > MLP_NPARAM) return;
+  float s = 0.f;
+  for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * (MLP_NPARAM + 1) + p];
+  if (p < MLP_NPARAM) grad[p] = s;
+  else if (loss) *loss = s / (4.0f * (float)n);
+}
+
+hipError_t launch_mlp_reduce(const float* partials, int nblocks, int64_t n, float* grad, float* loss,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, partials, nblocks, n, grad,
+                     loss);
+  return hipGetLastError();
+}
+
+// Adam (Kingma and Ba) with bias correction; step t >= 1
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, float c1, float c2, float lr, float b1,
+                                              float b2, float eps) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= MLP_NPARAM) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+hipError_t launch_adam(float* params, float* m, float* v, const float* grad, int64_t t, float lr, float b1,
+                       float b2, float eps, hipStream_t s) {
+  const float c1 = (float)(1.0 - pow((double)b1, (double)t));
+  const float c2 = (float)(1.0 - pow((double)b2, (double)t));
+  hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, params, m, v, grad, c1, c2, lr, b1,
+                     b2, eps);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

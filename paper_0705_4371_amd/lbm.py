@@ -49,6 +49,14 @@ class lbm_es_stats(C.Structure):
     ]
 
 
+class lbm_solve_stats(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("n_infeasible", C.c_int64), ("n_fallback", C.c_int64), ("n_failed", C.c_int64),
+        ("iter_hist", C.c_int64 * 16), ("mean_fp32_iters", C.c_double), ("mean_fp64_iters", C.c_double),
+        ("max_resid", C.c_double),
+    ]
+
+
 # name -> (restype, argtypes); the exported symbols of include/lbm.h
 _P = C.c_void_p
 SIGNATURES = {
@@ -65,6 +73,20 @@ SIGNATURES = {
     "lbm_kernel_time": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "lbm_layout": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "lbm_struct_sizes": (None, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "lbm_fstar_create": (C.c_int, [C.c_int64, _P, C.POINTER(_P)]),
+    "lbm_fstar_set_tolerance": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, C.c_int32]),
+    "lbm_fstar_solve": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P, _P, C.POINTER(lbm_solve_stats)]),
+    "lbm_fstar_free": (None, [_P]),
+    "lbm_mlp_create": (C.c_int, [C.c_uint64, C.POINTER(_P)]),
+    "lbm_mlp_get_params": (C.c_int, [_P, _P]),
+    "lbm_mlp_set_params": (C.c_int, [_P, _P]),
+    "lbm_mlp_set_norm": (C.c_int, [_P, _P]),
+    "lbm_mlp_get_norm": (C.c_int, [_P, _P]),
+    "lbm_mlp_forward": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
+    "lbm_mlp_loss_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
+    "lbm_mlp_adam_step": (C.c_int, [_P, _P, C.c_double, _P]),
+    "lbm_mlp_train": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P, _P]),
+    "lbm_mlp_free": (None, [_P]),
     "lbm_free": (None, [_P]),
     "lbm_strerror": (C.c_char_p, [C.c_int]),
     "lbm_last_error": (C.c_char_p, []),
@@ -224,3 +246,122 @@ class Lattice:
         b = C.c_int64()
         check(load().lbm_layout(self.ctx, C.byref(p), C.byref(b)), "lbm_layout")
         return p.value, b.value
+
+
+def _stream(stream):
+    import torch
+    return torch.cuda.current_stream().cuda_stream if stream is None else stream
+
+
+class FstarSolver:
+    """Workspace of the f*_M solver (lbm_fstar_*)."""
+
+    def __init__(self, max_n: int, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = _stream(stream)
+        h = C.c_void_p()
+        check(load().lbm_fstar_create(max_n, self.stream, C.byref(h)), "lbm_fstar_create")
+        self.h = h
+        self.max_n = max_n
+
+    def set_tolerance(self, tol=1e-10, tol32=2e-6, max32=16, max64=6):
+        check(load().lbm_fstar_set_tolerance(self.h, tol, tol32, max32, max64), "lbm_fstar_set_tolerance")
+
+    def solve(self, M, start=LBM_START_DEFAULT, net=None, stats=True, mu=None, iters=None, status=None):
+        """M: cuda float64 [4][n].  Returns (mu, iters, status, stats-or-None)."""
+        torch = self.torch
+        assert M.dtype == torch.float64 and M.is_cuda and M.dim() == 2 and M.shape[0] == 4
+        M = M.contiguous()
+        n = M.shape[1]
+        if mu is None:
+            mu = torch.empty_like(M)
+        if iters is None:
+            iters = torch.empty(n, dtype=torch.uint8, device=M.device)
+        if status is None:
+            status = torch.empty(n, dtype=torch.uint8, device=M.device)
+        st = lbm_solve_stats() if stats else None
+        rc = load().lbm_fstar_solve(self.h, M.data_ptr(), n, mu.data_ptr(), start,
+                                    net.h if net is not None else None, iters.data_ptr(),
+                                    status.data_ptr(), C.byref(st) if st is not None else None)
+        if rc not in (LBM_OK, LBM_E_NOCONV):
+            check(rc, "lbm_fstar_solve")
+        return mu, iters, status, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbm_fstar_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The warm-start network (lbm_mlp_*)."""
+
+    NPARAM = 4740
+
+    def __init__(self, seed: int = 0):
+        import torch
+        self.torch = torch
+        h = C.c_void_p()
+        check(load().lbm_mlp_create(seed, C.byref(h)), "lbm_mlp_create")
+        self.h = h
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.NPARAM, np.float32)
+        check(load().lbm_mlp_get_params(self.h, p.ctypes.data), "lbm_mlp_get_params")
+        return p
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == self.NPARAM
+        check(load().lbm_mlp_set_params(self.h, p.ctypes.data), "lbm_mlp_set_params")
+
+    def set_norm(self, in_shift, in_scale, out_shift, out_scale) -> None:
+        v = np.ascontiguousarray(np.concatenate([in_shift, in_scale, out_shift, out_scale]), np.float32)
+        check(load().lbm_mlp_set_norm(self.h, v.ctypes.data), "lbm_mlp_set_norm")
+
+    def get_norm(self) -> np.ndarray:
+        v = np.zeros(16, np.float32)
+        check(load().lbm_mlp_get_norm(self.h, v.ctypes.data), "lbm_mlp_get_norm")
+        return v
+
+    def forward(self, X, stream=None):
+        X = X.contiguous()
+        Y = self.torch.empty_like(X)
+        check(load().lbm_mlp_forward(self.h, X.data_ptr(), X.shape[0], Y.data_ptr(), _stream(stream)),
+              "lbm_mlp_forward")
+        return Y
+
+    def loss_grad(self, X, T, stream=None):
+        torch = self.torch
+        g = torch.empty(self.NPARAM, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        check(load().lbm_mlp_loss_grad(self.h, X.contiguous().data_ptr(), T.contiguous().data_ptr(), X.shape[0],
+                                       g.data_ptr(), loss.data_ptr(), _stream(stream)), "lbm_mlp_loss_grad")
+        return loss, g
+
+    def adam_step(self, grad, lr=1e-3, stream=None):
+        check(load().lbm_mlp_adam_step(self.h, grad.data_ptr(), lr, _stream(stream)), "lbm_mlp_adam_step")
+
+    def train(self, X, T, epochs, batch, lr=1e-3, seed=0, stream=None) -> np.ndarray:
+        losses = np.zeros(max(epochs, 1), np.float32)
+        check(load().lbm_mlp_train(self.h, X.contiguous().data_ptr(), T.contiguous().data_ptr(), X.shape[0],
+                                   epochs, batch, lr, seed, losses.ctypes.data, _stream(stream)), "lbm_mlp_train")
+        return losses[:epochs]
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbm_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,129 @@
+"""GPU parity of the f*_M solver (Newton on the four Lagrange multipliers,
+FP32 then FP64 iterations, damped-Newton fallback) with the CPU oracle.
+
+Bar: every feasible site reaches max_j |m_j(f*) - M_j| / rho <= 1e-10 (the
+residual recomputed from the returned multipliers by the oracle, in FP64);
+f*(mu) agrees with the oracle's f*_M within 1e-9 relative to rho (the
+multipliers are determined by M to within the residual times the inverse
+Hessian, O(1) here); infeasible moment vectors are flagged and receive the
+closed form.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from _gpu_common import say, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _rows():
+    vx, vy, _ = oracle.velocities(9)
+    return np.stack([np.ones(9), vx, vy, vx * vx + vy * vy]).astype(float)
+
+
+def _check_sites(M, mu, idx, tol=1e-10):
+    rows = _rows()
+    for i in idx:
+        f = oracle.fstar_from_mu(mu[:, i])
+        res = np.abs(rows @ f - M[:, i]).max() / M[0, i]
+        assert res <= tol * 1.01, (i, res)
+        mo, it, _ = oracle.fstar_newton(M[:, i])
+        fo = oracle.fstar_from_mu(mo)
+        assert np.abs(f - fo).max() <= 1e-9 * M[0, i], i
+
+
+def _all_residuals(torch, Mt, mut):
+    """max_j |m_j(exp(mu . m_i)) - M_j| / rho over all sites, FP64 on the GPU."""
+    rows = torch.tensor(_rows(), dtype=torch.float64, device=Mt.device)   # [4][9]
+    f = torch.exp(rows.T @ mut)                                            # [9][n]
+    m = rows @ f                                                           # [4][n]
+    return ((m - Mt).abs().max(0).values / Mt[0]).max().item()
+
+
+@pytest.mark.parametrize("start", [0, 1])
+def test_moment_field_all_starts(start):
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    say("fstar field start", start)
+    M = W.moment_field(nx=192, ny=100, seed=4)
+    Mt = torch.from_numpy(M).cuda()
+    s = lbm.FstarSolver(M.shape[1])
+    mu, iters, status, st = s.solve(Mt, start=start)
+    mu = mu.cpu().numpy()
+    assert st.n_failed == 0 and st.n_infeasible == 0
+    assert (status.cpu().numpy() <= 1).all()
+    assert st.max_resid <= 1e-10
+    assert _all_residuals(torch, Mt, torch.from_numpy(mu).cuda()) <= 1.01e-10
+    r = np.random.default_rng(0)
+    _check_sites(M, mu, r.integers(0, M.shape[1], 300))
+    it = iters.cpu().numpy()
+    # the rest start needs about as many updates as the oracle's Newton
+    if start == 0:
+        its = [oracle.fstar_newton(M[:, i], tol=1e-10)[1] for i in r.integers(0, M.shape[1], 200)]
+        assert abs(it.mean() - np.mean(its)) <= 1.5
+    say("  mean updates", it.mean(), "fp32", st.mean_fp32_iters, "fp64", st.mean_fp64_iters)
+    s.close()
+
+
+def test_wide_distribution_and_fallback():
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    M = W.random_moments(20000, 11, umax=0.45, energy_band=0.45)
+    feas = np.array([oracle.fstar_feasible(M[:, i]) for i in range(M.shape[1])])
+    Mt = torch.from_numpy(M).cuda()
+    s = lbm.FstarSolver(M.shape[1])
+    s.set_tolerance(max32=3, max64=2)   # small budgets force the fallback path
+    mu, iters, status, st = s.solve(Mt)
+    mu = mu.cpu().numpy()
+    stt = status.cpu().numpy()
+    assert st.n_infeasible == int((~feas).sum())
+    assert (stt[~feas] == 2).all() and (stt[feas] <= 1).all()
+    assert st.n_fallback > 0 and st.n_failed == 0
+    _check_sites(M, mu, np.flatnonzero(feas)[:200])
+    # infeasible sites carry the mass-momentum closed form
+    for i in np.flatnonzero(~feas)[:50]:
+        rho, u1, u2 = M[0, i], M[1, i] / M[0, i], M[2, i] / M[0, i]
+        if abs(u1) < 1 and abs(u2) < 1:
+            cf = oracle.qe_entropic_mm(9, rho, u1, u2)
+            assert np.abs(oracle.fstar_from_mu(mu[:, i]) - cf).max() <= 1e-12 * rho
+    s.close()
+
+
+def test_isothermal_energy_returns_closed_form():
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    r = np.random.default_rng(3)
+    n = 999
+    rho = r.uniform(0.5, 1.5, n)
+    u1, u2 = r.uniform(-0.1, 0.1, n), r.uniform(-0.1, 0.1, n)
+    rows = _rows()
+    M = np.stack([rows @ oracle.qe_entropic_mm(9, rho[i], u1[i], u2[i]) for i in range(n)], axis=1)
+    s = lbm.FstarSolver(n)
+    for start in (0, 1):
+        mu, iters, status, st = s.solve(torch.from_numpy(M).cuda(), start=start)
+        mu = mu.cpu().numpy()
+        assert np.abs(mu[3] - math.log(0.25)).max() < 1e-9
+        if start == 1:
+            assert iters.cpu().numpy().max() <= 1   # the closed form is already the answer
+    s.close()
+
+
+def test_full_size_moment_field():
+    """4096 x 2048 sites: every residual <= 1e-10 (checked on the GPU in FP64),
+    a sample of sites against the oracle."""
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    say("fstar full size")
+    M = W.moment_field()
+    Mt = torch.from_numpy(M).cuda()
+    s = lbm.FstarSolver(M.shape[1])
+    mu, iters, status, st = s.solve(Mt)
+    assert st.n_failed == 0 and st.n_infeasible == 0
+    assert _all_residuals(torch, Mt, mu) <= 1.01e-10
+    mun = mu.cpu().numpy()
+    _check_sites(M, mun, np.random.default_rng(1).integers(0, M.shape[1], 200))
+    s.close()

@@ -1,0 +1,135 @@
+"""GPU parity of the warm-start MLP (BF16 matrix-core forward, backward and
+Adam) with the CPU oracle, which emulates the same BF16 rounding points.
+
+Bars (derived in the design notes): the GPU accumulates in FP32 where the
+oracle uses FP64, so a BF16 rounding of a hidden activation can fall on the
+other side of a tie; per sample this happens with probability ~1e-4 per
+activation and moves an output by at most ~1e-2 of its scale.  Hence:
+outputs of 99% of samples within 1e-4 relative, all within 3e-2; gradients
+within 2e-3 of the largest gradient component per entry and 1e-3 in norm;
+Adam moments and weights (FP32 vs FP64) within 1e-6 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from _gpu_common import say, torch_gpu
+
+pytestmark = pytest.mark.gpu
+NP = oracle.MLP_NPARAM
+
+
+def _net(seed):
+    import paper_0705_4371_amd.lbm as lbm
+    return lbm.Mlp(seed)
+
+
+def test_forward_matches_oracle():
+    torch = torch_gpu()
+    say("mlp forward")
+    net = _net(7)
+    p = net.get_params().astype(np.float64)
+    # non-zero biases too
+    r = np.random.default_rng(1)
+    p[256:320] = 0.1 * r.standard_normal(64)
+    p[4416:4480] = 0.1 * r.standard_normal(64)
+    p[4736:4740] = 0.1 * r.standard_normal(4)
+    net.set_params(p.astype(np.float32))
+    p = net.get_params().astype(np.float64)
+    X = r.standard_normal((1037, 4)).astype(np.float32)   # ragged: not a multiple of 16 or 64
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    Yo = oracle.mlp_forward(p, X.astype(np.float64), bf16=True)
+    scale = np.abs(Yo).max()
+    err = np.abs(Y - Yo).max(axis=1) / scale
+    assert np.quantile(err, 0.99) <= 1e-4, np.quantile(err, 0.99)
+    assert err.max() <= 3e-2, err.max()
+    # and the emulation matters: the FP64 network differs by more
+    Y64 = oracle.mlp_forward(p, X.astype(np.float64), bf16=False)
+    assert np.abs(Y64 - Yo).max() > 10 * np.quantile(np.abs(Y - Yo), 0.5)
+    net.close()
+
+
+def test_loss_grad_matches_oracle():
+    torch = torch_gpu()
+    say("mlp grad")
+    net = _net(8)
+    p = net.get_params().astype(np.float64)
+    r = np.random.default_rng(2)
+    X = r.standard_normal((2053, 4)).astype(np.float32)
+    T = r.standard_normal((2053, 4)).astype(np.float32)
+    loss, g = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    lo, go = oracle.mlp_loss_grad(p, X.astype(np.float64), T.astype(np.float64), bf16=True)
+    assert abs(loss.item() - lo) <= 1e-4 * lo
+    gmax = np.abs(go).max()
+    assert np.abs(g - go).max() <= 2e-3 * gmax, np.abs(g - go).max() / gmax
+    assert np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
+    # deterministic (fixed-order reduction)
+    _, g2 = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    assert np.array_equal(g2.cpu().numpy().astype(np.float64), g)
+    net.close()
+
+
+def test_adam_matches_oracle():
+    torch = torch_gpu()
+    net = _net(9)
+    p = net.get_params().astype(np.float64)
+    m = np.zeros(NP)
+    v = np.zeros(NP)
+    r = np.random.default_rng(3)
+    for t in range(1, 4):
+        gr = (1e-3 * r.standard_normal(NP)).astype(np.float32)
+        net.adam_step(torch.from_numpy(gr).cuda(), lr=1e-3)
+        oracle.adam_step(p, m, v, gr.astype(np.float64), t, lr=1e-3)
+    q = net.get_params().astype(np.float64)
+    assert np.abs(q - p).max() <= 1e-6 * max(1.0, np.abs(p).max())
+    net.close()
+
+
+def _harvest(torch, n, seed, umax=0.1, band=0.05):
+    import paper_0705_4371_amd.lbm as lbm
+    M = W.random_moments(n, seed, umax=umax, energy_band=band)
+    Mt = torch.from_numpy(M).cuda()
+    s = lbm.FstarSolver(n)
+    mu, _, status, st = s.solve(Mt)
+    assert st.n_failed == 0
+    s.close()
+    return M, mu.cpu().numpy()
+
+
+def test_training_reduces_loss_and_newton_work():
+    """Train on solver-generated pairs; on held-out moments the network start
+    needs fewer Newton updates than the rest start, with the same residual."""
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    say("mlp train")
+    M, mu = _harvest(torch, 1 << 16, 21)
+    net = lbm.Mlp(5)
+    norm = W.mlp_norm()
+    net.set_norm(*norm)
+    nm = net.get_norm()
+    X = oracle.mlp_features(M, nm).astype(np.float32)
+    T = oracle.mlp_targets(M, mu, nm).astype(np.float32)
+    losses = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), epochs=20, batch=4096, lr=3e-3,
+                       seed=5)
+    say("  losses", losses[0], losses[-1])
+    assert losses[-1] < 0.05 * losses[0]
+    Mh = W.random_moments(20000, 104)
+    Mt = torch.from_numpy(Mh).cuda()
+    s = lbm.FstarSolver(Mh.shape[1])
+    _, it0, _, st0 = s.solve(Mt, start=lbm.LBM_START_DEFAULT)
+    mu1, it1, _, st1 = s.solve(Mt, start=lbm.LBM_START_MLP, net=net)
+    say("  updates rest %.3f net %.3f" % (it0.float().mean().item(), it1.float().mean().item()))
+    assert st1.n_failed == 0 and st1.max_resid <= 1e-10
+    assert it1.float().mean().item() < it0.float().mean().item()
+    # the network start itself against the oracle's emulated forward
+    warm = oracle.mlp_warm_start(net.get_params().astype(np.float64), nm, Mh[:, :500])
+    f_net = np.array([oracle.fstar_from_mu(np.r_[warm[0, i] + math.log(Mh[0, i]), warm[1:, i]])
+                      for i in range(500)])
+    f_ref = np.array([oracle.fstar_from_mu(mu1.cpu().numpy()[:, i]) for i in range(500)])
+    assert np.abs(f_net - f_ref).max() < 5e-2 * Mh[0, :500].max()
+    s.close()
+    net.close()

@@ -161,3 +161,15 @@ CONFIGS = {
     "cylinder_2400x800_re20000_fstarM": lambda: cylinder(nx=2400, ny=800, side=80, centre=(600, 400),
                                                          re=20000.0, k=256, qe=QE_ENTROPIC_M),
 }
+
+
+def mlp_norm():
+    """Fixed input/output scalings of the warm-start network, sized for the
+    moment distribution above (|u| <= 0.1, energy within 5% of isothermal):
+    features (u1, u2, 2E/rho, |u|^2) and targets (mu0 - ln rho, mu1, mu2, mu3)
+    are mapped to O(1) by x = (value - shift) * scale."""
+    in_shift = [0.0, 0.0, 2.0 / 3.0, 0.005]
+    in_scale = [20.0, 20.0, 20.0, 200.0]
+    out_shift = [math.log(4.0 / 9.0), 0.0, 0.0, -math.log(4.0)]
+    out_scale = [10.0, 5.0, 5.0, 10.0]
+    return in_shift, in_scale, out_shift, out_scale
