@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp"):
+    for name in ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar_dev.hpp"):
         with open(os.path.join(ROOT, "paper_0705_4371_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--cpu-nx", type=int, default=8192)
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB float32 tensor 10 times (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -100,6 +102,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain device copy of known size: 2^28 floats (1 GiB) read and written
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                          "copy_GBps": 2 * (1 << 30) / dt / 1e9}), flush=True)
+        return
     prec = lbm.LBM_FP64 if args.precision == "fp64" else lbm.LBM_FP32
     d, rho, u = W.shear_layer(nx=args.nx, ny=args.ny)
     workload = "shear_%dx%d" % (args.nx, args.ny)
@@ -123,6 +138,12 @@ def main():
     dt = time.perf_counter() - t0
     k_ms, k_n = lat.kernel_time()
     lat.set_timing(False)
+    # the same number of steps through the captured graphs (no events)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t1
     st, _, _ = lat.stats()
     ms_per_step = dt * 1e3 / args.steps
     mlups = n_sites * args.steps / dt / 1e6
@@ -154,6 +175,7 @@ def main():
                      "bytes_per_site": bytes_per_site},
         "ehrenfest": {"n_above_delta_last": st.n_above_delta, "selected_total": st.total_selected,
                       "mass": st.mass},
+        "graph_replay_MLUPS": round(n_sites * args.steps / dt_graph / 1e6, 1),
     }
     lat.close()
     if not args.no_cpu_baseline:

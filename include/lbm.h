@@ -66,12 +66,15 @@ typedef struct lbm_config {
   double nu;          /* kinematic viscosity > 0; beta = 1/(1 + 6 nu)           */
   double delta;       /* Ehrenfests' tolerance on Delta S, >= 0 (+inf: off)     */
   int32_t k;          /* at most k Ehrenfests' steps per time step, >= 0        */
-  int32_t fstar_start;/* LBM_START_* (LBM_QE_ENTROPIC_M only)                   */
+  int32_t fstar_start;/* LBM_START_* (LBM_QE_ENTROPIC_M only): start of the
+                         per-site Newton solve in every step; the residual
+                         target is 1e-10 (FP32 contexts) or 1e-13 (FP64)      */
   int32_t bc[4];      /* west, east, south, north                               */
   double inlet_rho;   /* inlet state for LBM_BC_INLET_EQ                        */
   double inlet_u[2];
   int64_t solid_x0, solid_y0, solid_w, solid_h; /* solid square (w == 0: none)  */
-  const lbm_mlp* net; /* warm-start network for LBM_START_MLP, else NULL        */
+  const lbm_mlp* net; /* warm-start network for LBM_START_MLP, else NULL; must
+                         outlive the context                                   */
   void* stream;       /* hipStream_t used for all work of the context (0: null) */
 } lbm_config;
 
@@ -80,14 +83,17 @@ typedef struct lbm_es_stats {
   int64_t n_above_delta; /* last step: sites with Delta S > delta                  */
   int64_t n_selected;    /* last step: sites returned to quasiequilibrium          */
   int64_t n_invalid;     /* last step: sites with Delta S = +inf (f < 0 or f* <= 0) */
-  int64_t n_fallback;    /* last step: f*_M sites that used the fallback            */
+  int64_t n_fallback;    /* last step, f*_M only: sites whose first Newton pass
+                            missed the tolerance (re-solved by damped Newton from
+                            the rest start) plus infeasible sites (closed form)   */
   int64_t total_selected;/* all steps since init                                   */
-  int64_t nonfinite;     /* sticky: non-finite post-collision values were written  */
-  int64_t pad0;
+  int64_t nonfinite;     /* sticky: a step met non-finite populations              */
+  int64_t newton_updates;/* last step, f*_M only: Newton updates over all sites    */
   double kth_dS;         /* last step: smallest selected Delta S (0 if none)       */
   double max_dS;         /* last step: largest Delta S above delta (0 if none)     */
-  double mass, mom[2], energy; /* last step: FP64 sums over fluid sites of rho,
-                                  rho u1, rho u2, 2E of the pre-collision state   */
+  double mass, mom[2], energy; /* FP64 sums over fluid sites of rho, rho u1,
+                                  rho u2, 2E of the current pre-collision state
+                                  f(x, t) (conservation diagnostics)            */
 } lbm_es_stats;
 
 /* Fills *cfg with defaults: D2Q9, polynomial QE, FP32, LBGK, 64 x 64

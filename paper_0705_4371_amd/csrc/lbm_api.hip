@@ -16,6 +16,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_launch.hpp"
+#include "lbm_internal.hpp"
 
 using namespace lbm;
 
@@ -75,6 +76,15 @@ struct lbm_ctx {
   double* sel_ds = nullptr;
   DevStats* st = nullptr;
   double* partials = nullptr;
+  // f*_M quasiequilibrium (LBM_QE_ENTROPIC_M)
+  double* Mbuf = nullptr;
+  double* mubuf = nullptr;
+  float* warm = nullptr;
+  uint32_t* fctr = nullptr;
+  uint32_t* fail_list = nullptr;
+  FstarStats* fstats = nullptr;
+  FstarArgs fa{};
+  int fkind = START_REST;
 };
 
 extern "C" {
@@ -117,8 +127,13 @@ int lbm_validate_config(const lbm_config* c) {
     return fail(LBM_E_INVAL, "lattice must be LBM_D1Q3 (3) or LBM_D2Q9 (9), got %d", c->lattice);
   if (c->qe != LBM_QE_POLY && c->qe != LBM_QE_ENTROPIC_MM && c->qe != LBM_QE_ENTROPIC_M)
     return fail(LBM_E_INVAL, "qe must be one of LBM_QE_*, got %d", c->qe);
-  if (c->qe == LBM_QE_ENTROPIC_M)
-    return fail(LBM_E_INVAL, "LBM_QE_ENTROPIC_M time stepping is not available in this library build");
+  if (c->qe == LBM_QE_ENTROPIC_M) {
+    if (c->lattice != LBM_D2Q9) return fail(LBM_E_INVAL, "LBM_QE_ENTROPIC_M needs D2Q9");
+    if (c->fstar_start != LBM_START_DEFAULT && c->fstar_start != LBM_START_CLOSED_FORM &&
+        c->fstar_start != LBM_START_MLP)
+      return fail(LBM_E_INVAL, "fstar_start must be one of LBM_START_*");
+    if (c->fstar_start == LBM_START_MLP && !c->net) return fail(LBM_E_INVAL, "LBM_START_MLP needs cfg->net");
+  }
   if (c->precision != LBM_FP32 && c->precision != LBM_FP64)
     return fail(LBM_E_INVAL, "precision must be LBM_FP32 or LBM_FP64, got %d", c->precision);
   if (c->collision != LBM_COLL_LBGK)
@@ -203,7 +218,7 @@ static void ctx_release(lbm_ctx* c) {
   for (auto& e : c->ev_used) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& e : c->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   void* ptrs[] = {c->buf[0], c->buf[1], c->ctr, c->screen, c->cand, c->bnd, c->hist, c->sel, c->sel_ds,
-                  c->st, c->partials};
+                  c->st, c->partials, c->Mbuf, c->mubuf, c->warm, c->fctr, c->fail_list, c->fstats};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -215,6 +230,22 @@ static StepArgs args_for(const lbm_ctx* c, int src, int dst) {
   a.A = c->buf[src];
   a.B = c->buf[dst];
   return a;
+}
+
+// one time step from buffer src into buffer dst; for the f*_M
+// quasiequilibrium the moments, the (optional) network start and the Newton
+// solve for every site run first
+static hipError_t step_once(const lbm_ctx* c, int src, int dst, bool pull, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1) {
+  const StepArgs a = args_for(c, src, dst);
+  if (c->cfg.qe == LBM_QE_ENTROPIC_M) {
+    hipError_t e = launch_moments_M(a, pull, s);
+    if (e == hipSuccess && c->fkind == START_WARM)
+      e = launch_mlp_warm(c->cfg.net->params, c->cfg.net->norm, c->Mbuf, c->N, c->warm, s);
+    if (e == hipSuccess) e = launch_fstar(c->fa, c->fkind, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_step(a, pull, s, e0, e1);
 }
 
 int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const double* twoE0,
@@ -293,7 +324,34 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   ALLOC(c->sel, sizeof(uint32_t) * kcap);
   ALLOC(c->sel_ds, sizeof(double) * kcap);
   ALLOC(c->st, sizeof(DevStats));
-  ALLOC(c->partials, sizeof(double) * 4 * (size_t)a.nblocks);
+  ALLOC(c->partials, sizeof(double) * 4 * 1024);
+  if (cfg->qe == LBM_QE_ENTROPIC_M) {
+    ALLOC(c->Mbuf, sizeof(double) * 4 * ncap);
+    ALLOC(c->mubuf, sizeof(double) * 4 * ncap);
+    ALLOC(c->fctr, 16);
+    ALLOC(c->fail_list, sizeof(uint32_t) * ncap);
+    ALLOC(c->fstats, sizeof(FstarStats));
+    if (cfg->fstar_start == LBM_START_MLP) ALLOC(c->warm, sizeof(float) * 4 * ncap);
+    FstarArgs& f = c->fa;
+    f.M = c->Mbuf;
+    f.n = c->N;
+    f.mu = c->mubuf;
+    f.warm = c->warm;
+    f.iters = nullptr;
+    f.status = nullptr;
+    f.ctr = c->fctr;
+    f.fail_list = c->fail_list;
+    f.stats = c->fstats;
+    f.tol = cfg->precision == LBM_FP64 ? 1e-13 : 1e-10;
+    f.tol32 = 2e-6f;
+    f.max32 = 16;
+    f.max64 = 6;
+    c->fkind = cfg->fstar_start == LBM_START_CLOSED_FORM ? START_CLOSED
+               : cfg->fstar_start == LBM_START_MLP        ? START_WARM
+                                                          : START_REST;
+    a.Mbuf = c->Mbuf;
+    a.mu = c->mubuf;
+  }
 #undef ALLOC
   a.ctr = c->ctr;
   a.screen = c->screen;
@@ -306,7 +364,14 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   a.partials = c->partials;
 
   hipError_t e = launch_clear(args_for(c, 0, 0), c->stream);
-  if (e == hipSuccess) e = launch_init(args_for(c, 1, 0), rho0, u0, twoE0, c->stream);
+  if (cfg->qe == LBM_QE_ENTROPIC_M) {
+    // f(x, 0) = f*_M of the initial moments (rest start, then the fallback)
+    if (e == hipSuccess) e = launch_init_M_moments(args_for(c, 1, 0), rho0, u0, twoE0, c->stream);
+    if (e == hipSuccess) e = launch_fstar(c->fa, START_REST, c->stream);
+    if (e == hipSuccess) e = launch_init_M_pops(args_for(c, 1, 0), c->stream);
+  } else if (e == hipSuccess) {
+    e = launch_init(args_for(c, 1, 0), rho0, u0, twoE0, c->stream);
+  }
   if (e != hipSuccess) {
     ctx_release(c);
     return fail(LBM_E_DEVICE, "init kernels: %s", hipGetErrorString(e));
@@ -331,7 +396,7 @@ static int ensure_graph(lbm_ctx* c, int from) {
   int s = from;
   hipError_t err = hipSuccess;
   for (int t = 0; t < GRAPH_STEPS && err == hipSuccess; ++t) {
-    err = launch_step(args_for(c, s, 1 - s), true, c->cap, nullptr, nullptr);
+    err = step_once(c, s, 1 - s, true, c->cap, nullptr, nullptr);
     s = 1 - s;
   }
   hipGraph_t gr = nullptr;
@@ -355,7 +420,7 @@ static int timed_launch(lbm_ctx* c, bool pull) {
     HIPCHK(hipEventCreate(&ev.second));
   }
   c->ev_used.push_back(ev);
-  HIPCHK(launch_step(args_for(c, c->cur, 1 - c->cur), pull, c->stream, ev.first, ev.second));
+  HIPCHK(step_once(c, c->cur, 1 - c->cur, pull, c->stream, ev.first, ev.second));
   return LBM_OK;
 }
 
@@ -385,7 +450,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
         if ((rc = timed_launch(c, pull))) return rc;
         if (c->ev_used.size() >= 1024 && (rc = drain_events(c))) return rc;
       } else {
-        HIPCHK(launch_step(args_for(c, c->cur, 1 - c->cur), pull, c->stream, nullptr, nullptr));
+        HIPCHK(step_once(c, c->cur, 1 - c->cur, pull, c->stream, nullptr, nullptr));
       }
       c->cur = 1 - c->cur;
       c->canonical = false;
@@ -400,7 +465,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       n -= GRAPH_STEPS;
       continue;
     }
-    HIPCHK(launch_step(args_for(c, c->cur, 1 - c->cur), true, c->stream, nullptr, nullptr));
+    HIPCHK(step_once(c, c->cur, 1 - c->cur, true, c->stream, nullptr, nullptr));
     c->cur = 1 - c->cur;
     c->step++;
     n--;
@@ -440,7 +505,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* rhou, double* e2) {
 int lbm_ehrenfest_stats(lbm_ctx* c, lbm_es_stats* out, int64_t* sel, double* sel_dS, int64_t cap) {
   if (!c || !out) return fail(LBM_E_INVAL, "ctx and out are required");
   if (cap < 0) return fail(LBM_E_INVAL, "sel_cap must be >= 0");
-  HIPCHK(launch_finalize(c->args, c->stream));
+  HIPCHK(launch_sums(args_for(c, c->cur, c->cur), !c->canonical, c->stream));
   DevStats st;
   uint32_t ctr[C_COUNT];
   HIPCHK(hipMemcpyAsync(&st, c->st, sizeof(st), hipMemcpyDeviceToHost, c->stream));
@@ -452,6 +517,13 @@ int lbm_ehrenfest_stats(lbm_ctx* c, lbm_es_stats* out, int64_t* sel, double* sel
   out->n_selected = (int64_t)st.n_sel;
   out->n_invalid = (int64_t)st.n_invalid;
   out->n_fallback = 0;
+  out->newton_updates = 0;
+  if (c->cfg.qe == LBM_QE_ENTROPIC_M) {
+    FstarStats fs;
+    HIPCHK(hipMemcpy(&fs, c->fstats, sizeof(fs), hipMemcpyDeviceToHost));
+    out->n_fallback = (int64_t)(fs.fallback + fs.infeasible);
+    out->newton_updates = (int64_t)(fs.sum32 + fs.sum64);
+  }
   out->total_selected = (int64_t)st.total_sel;
   out->nonfinite = ctr[C_NONFINITE] ? 1 : 0;
   out->kth_dS = st.kth;

@@ -11,6 +11,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_fstar.hpp"
+#include "lbm_internal.hpp"
 
 using namespace lbm;
 
@@ -23,32 +24,6 @@ int lbm_internal_fail(int code, const char* fmt, ...);
     hipError_t e_ = (expr);                                                                        \
     if (e_ != hipSuccess) return lbm_internal_fail(LBM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
-
-struct lbm_fstar {
-  int64_t cap = 0;
-  hipStream_t stream = nullptr;
-  double tol = 1e-10;
-  float tol32 = 2e-6f;
-  int max32 = 16, max64 = 6;
-  uint32_t* ctr = nullptr;
-  uint32_t* fail_list = nullptr;
-  float* warm = nullptr;
-  FstarStats* stats = nullptr;
-};
-
-struct lbm_mlp {
-  float* params = nullptr;  // FP32 master weights [4740]
-  float* m = nullptr;
-  float* v = nullptr;
-  float* grad = nullptr;
-  float* partials = nullptr;  // [256][4741]
-  float* loss = nullptr;      // per-batch losses of the current epoch
-  int64_t loss_cap = 0;
-  int32_t* idx = nullptr;
-  int64_t idx_cap = 0;
-  int64_t t = 0;  // Adam step
-  MlpNorm norm{};
-};
 
 // SplitMix64 (Steele, Lea and Flood 2014)
 static uint64_t splitmix64(uint64_t x) {

@@ -82,33 +82,48 @@ __device__ __forceinline__ Moments<Q, T> moments(const T* f) {
 
 // Polynomial quasiequilibrium.  D1Q3: Sec. 4.1's formulas.  D2Q9: the
 // second-order polynomial W_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u) of the
-// LBGK literature the paper cites for it.
+// LBGK literature the paper cites for it.  Written as f*_i = W_i rho p_i;
+// the brackets p_i are returned for the Delta S screen.
 template <int Q, typename T>
-__device__ __forceinline__ void qe_poly(T rho, T ux, T uy, T* fs) {
+__device__ __forceinline__ void qe_poly_br(T rho, T ux, T uy, T* fs, T* p) {
   if constexpr (Q == 9) {
     const T uu = ux * ux + uy * uy;
     const T base = T(1) - T(1.5) * uu;  // 1 - 3/2 u.u
     const T r0 = rho * T(4.0 / 9.0), r1 = rho * T(1.0 / 9.0), r2 = rho * T(1.0 / 36.0);
-    fs[0] = r0 * base;
+    p[0] = base;
     // axis velocities: c.u = +-ux, +-uy
     const T ax = base + T(4.5) * ux * ux, ay = base + T(4.5) * uy * uy;
-    fs[1] = r1 * (ax + T(3) * ux);
-    fs[3] = r1 * (ax - T(3) * ux);
-    fs[2] = r1 * (ay + T(3) * uy);
-    fs[4] = r1 * (ay - T(3) * uy);
+    p[1] = ax + T(3) * ux;
+    p[3] = ax - T(3) * ux;
+    p[2] = ay + T(3) * uy;
+    p[4] = ay - T(3) * uy;
     // diagonals: c.u = +-(ux + uy), +-(ux - uy)
-    const T p = ux + uy, q = ux - uy;
-    const T dp = base + T(4.5) * p * p, dq = base + T(4.5) * q * q;
-    fs[5] = r2 * (dp + T(3) * p);  // NE  (+1,+1)
-    fs[7] = r2 * (dp - T(3) * p);  // SW  (-1,-1)
-    fs[8] = r2 * (dq + T(3) * q);  // SE  (+1,-1)
-    fs[6] = r2 * (dq - T(3) * q);  // NW  (-1,+1)
+    const T a = ux + uy, b = ux - uy;
+    const T dp = base + T(4.5) * a * a, dq = base + T(4.5) * b * b;
+    p[5] = dp + T(3) * a;  // NE  (+1,+1)
+    p[7] = dp - T(3) * a;  // SW  (-1,-1)
+    p[8] = dq + T(3) * b;  // SE  (+1,-1)
+    p[6] = dq - T(3) * b;  // NW  (-1,+1)
+    fs[0] = r0 * p[0];
+    #pragma unroll
+    for (int i = 1; i < 5; ++i) fs[i] = r1 * p[i];
+    #pragma unroll
+    for (int i = 5; i < 9; ++i) fs[i] = r2 * p[i];
   } else {
     const T u = ux;
-    fs[0] = (T(2) * rho / T(3)) * (T(1) - T(1.5) * u * u);
-    fs[1] = (rho / T(6)) * (T(1) - T(3) * u + T(3) * u * u);
-    fs[2] = (rho / T(6)) * (T(1) + T(3) * u + T(3) * u * u);
+    p[0] = T(1) - T(1.5) * u * u;
+    p[1] = T(1) - T(3) * u + T(3) * u * u;
+    p[2] = T(1) + T(3) * u + T(3) * u * u;
+    fs[0] = (T(2) * rho / T(3)) * p[0];
+    fs[1] = (rho / T(6)) * p[1];
+    fs[2] = (rho / T(6)) * p[2];
   }
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ void qe_poly(T rho, T ux, T uy, T* fs) {
+  T p[Q];
+  qe_poly_br<Q, T>(rho, ux, uy, fs, p);
 }
 
 // Entropic quasiequilibrium with mass and momentum constraints, closed
@@ -150,11 +165,14 @@ __device__ __forceinline__ void qe_entropic_mm(T rho, T ux, T uy, T* fs) {
   }
 }
 
+template <typename T> __device__ __forceinline__ T inv_of(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);
+  else return T(1) / x;
+}
+
 template <int Q, int QE, typename T>
 __device__ __forceinline__ void qe_eval(const Moments<Q, T>& m, T* fs) {
-  T inv;
-  if constexpr (sizeof(T) == 4) inv = __builtin_amdgcn_rcpf(m.rho);
-  else inv = T(1) / m.rho;
+  const T inv = inv_of(m.rho);
   const T ux = m.jx * inv, uy = m.jy * inv;
   if constexpr (QE == QE_POLY) qe_poly<Q, T>(m.rho, ux, uy, fs);
   else qe_entropic_mm<Q, T>(m.rho, ux, uy, fs);
@@ -187,6 +205,32 @@ __device__ __forceinline__ float dS_screen(const float* f, const float* fs) {
     wild |= !(a >= 0.0f) | !(b > 0.0f) | !(__builtin_fabsf(s) <= 0.5f);
   }
   return wild ? __builtin_inff() : acc;
+}
+
+// FP32 screen for the polynomial quasiequilibrium f*_i = W_i rho p_i, free
+// of reciprocals: with a = f_i, b = f*_i > 0, a ln(a/b) - a + b <= (a-b)^2/b
+// (from ln x <= x - 1), and 1/p <= 2p^2 - 5p + 4 for p in [1/2, 3/2], so
+//   Delta S <= (1/rho) sum_i (f_i - f*_i)^2 (2 p_i^2 - 5 p_i + 4) / W_i.
+// Returns +inf when some f_i < 0, some p_i is outside [1/2, 3/2] (this
+// includes f*_i <= 0), or a value is not finite.
+template <int Q>
+__device__ __forceinline__ float dS_bound_poly(const float* f, const float* fs, const float* p, float inv_rho) {
+  float acc = 0.0f;
+  float fmin = f[0], pmin = p[0], pmax = p[0];
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float d = f[i] - fs[i];
+    const float q = __builtin_fmaf(p[i], __builtin_fmaf(2.0f, p[i], -5.0f), 4.0f);
+    acc = __builtin_fmaf(d * d * (float)(1.0 / Lat<Q>::w(i)), q, acc);
+    if (i > 0) {
+      fmin = fminf(fmin, f[i]);
+      pmin = fminf(pmin, p[i]);
+      pmax = fmaxf(pmax, p[i]);
+    }
+  }
+  const float u = acc * inv_rho;
+  const bool ok = fmin >= 0.0f && pmin >= 0.5f && pmax <= 1.5f && u <= 3.0e38f;
+  return ok ? u : __builtin_inff();
 }
 
 // FP64 Delta S (Sec. 3.3 Kullback form, generalised by -f + f* so that it

@@ -4,8 +4,7 @@
 // One time step is four kernels on one stream:
 //   k_step   fused pull-stream + boundary rules + moments + f* + FP32 Delta S
 //            screen + LBGK collision + write; screened sites are appended to
-//            a list (one atomic per wavefront); FP64 block partials of the
-//            moments for the conservation sums.            (HBM bound)
+//            a list (one atomic per wavefront).             (HBM bound)
 //   k_rank   FP64 Delta S of the screened sites; sites with Delta S > delta
 //            become candidates (site, Delta S) and feed a 2^15-bin histogram
 //            of the top bits of Delta S.                    (O(#screened))
@@ -23,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lbm_device.hpp"
+#include "lbm_fstar_dev.hpp"
 #include "lbm_launch.hpp"
 
 namespace lbm {
@@ -75,6 +75,17 @@ __device__ __forceinline__ void load_site(const T* __restrict__ A, const Geom& g
     f[i] = PULL ? pull_general<T, Q>(A, g, x, y, i) : A[(int64_t)i * g.plane + y * g.pitch + x];
 }
 
+// f*_M populations of site s from the multiplier buffer mu [4][N]
+template <typename T>
+__device__ __forceinline__ void fstar_from_mu_buf(const double* __restrict__ mu, int64_t N, int64_t s, T* fs) {
+  if constexpr (sizeof(T) == 4) {
+    fstar_pop<float>(__expf((float)mu[s]), __expf((float)mu[N + s]), __expf((float)mu[2 * N + s]),
+                     __expf((float)mu[3 * N + s]), fs);
+  } else {
+    fstar_pop<double>(::exp(mu[s]), ::exp(mu[N + s]), ::exp(mu[2 * N + s]), ::exp(mu[3 * N + s]), fs);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_step
 // ---------------------------------------------------------------------------
@@ -116,16 +127,35 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   }
 
   const Moments<Q, T> m = moments<Q, T>(f);
-  T fs[Q];
-  qe_eval<Q, QE, T>(m, fs);
+  T fs[Q], pb[Q];
+  const T inv = inv_of(m.rho);
+  const T ux = m.jx * inv, uy = m.jy * inv;
+  if constexpr (QE == QE_POLY) qe_poly_br<Q, T>(m.rho, ux, uy, fs, pb);
+  else if constexpr (QE == QE_ENTROPIC_MM) qe_entropic_mm<Q, T>(m.rho, ux, uy, fs);
+  else {
+    if (fluid) fstar_from_mu_buf<T>(a.mu, g.nx * g.ny, x + y * g.nx, fs);
+    else {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) fs[i] = f[i];
+    }
+  }
 
-  // FP32 screen of Delta S; screened sites are re-ranked in FP64 by k_rank
+  // FP32 screen of Delta S (an upper bound, or an estimate with a margin);
+  // screened sites are re-ranked in FP64 by k_rank
   bool scr = false;
   if (g.ds_on && fluid) {
     float ff[Q], fsf[Q];
     #pragma unroll
     for (int i = 0; i < Q; ++i) { ff[i] = (float)f[i]; fsf[i] = (float)fs[i]; }
-    const float ds = dS_screen<Q>(ff, fsf);
+    float ds;
+    if constexpr (QE == QE_POLY) {
+      float pf[Q];
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) pf[i] = (float)pb[i];
+      ds = dS_bound_poly<Q>(ff, fsf, pf, (float)inv);
+    } else {
+      ds = dS_screen<Q>(ff, fsf);
+    }
     const float thr = a.thr_a - a.thr_b * __builtin_sqrtf(fmaxf((float)m.rho, 0.0f));
     scr = !(ds < thr);
   }
@@ -149,27 +179,9 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
     if (scr) a.screen[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(x + y * g.nx);
   }
 
-  // FP64 block partials of rho, rho u1, rho u2, 2E (pre-collision)
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  if (fluid) { s0 = (double)m.rho; s1 = (double)m.jx; s2 = (double)m.jy; s3 = (double)m.e2; }
-  #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_xor(s0, off);
-    s1 += __shfl_xor(s1, off);
-    s2 += __shfl_xor(s2, off);
-    s3 += __shfl_xor(s3, off);
-  }
-  __shared__ double red[STEP_TX / 64][4];
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { red[wv][0] = s0; red[wv][1] = s1; red[wv][2] = s2; red[wv][3] = s3; }
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    double s = 0.0;
-    #pragma unroll
-    for (int w = 0; w < STEP_TX / 64; ++w) s += red[w][threadIdx.x];
-    a.partials[b * 4 + threadIdx.x] = s;
-    if (!__builtin_isfinite(s)) atomicOr(&a.ctr[C_NONFINITE], 1u);
-  }
+  // sticky flag for non-finite populations (a non-finite f gives a non-finite rho)
+  if (__ballot(fluid && !__builtin_isfinite(m.rho)) && (threadIdx.x & 63) == 0)
+    atomicOr(&a.ctr[C_NONFINITE], 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -190,7 +202,20 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
     for (int i = 0; i < Q; ++i) fd[i] = (double)fT[i];
     const Moments<Q, double> m = moments<Q, double>(fd);
     double fs[Q];
-    qe_eval<Q, QE, double>(m, fs);
+    if constexpr (QE == QE_ENTROPIC_M) {
+      // the solver's multipliers polished to FP64 round-off for the ranking
+      const int64_t N = g.nx * g.ny;
+      const double mus[4] = {a.mu[site], a.mu[N + site], a.mu[2 * N + site], a.mu[3 * N + site]};
+      const double ir = 1.0 / m.rho;
+      if (feasible(m.rho, m.jx * ir, m.jy * ir, m.e2 * ir)) {
+        const FS<double> p = polish64(mus, m.rho, m.jx * ir, m.jy * ir, m.e2 * ir, 3);
+        fstar_pop<double>(m.rho * p.a, p.X, p.Y, p.Z, fs);
+      } else {
+        fstar_pop<double>(::exp(mus[0]), ::exp(mus[1]), ::exp(mus[2]), ::exp(mus[3]), fs);
+      }
+    } else {
+      qe_eval<Q, QE, double>(m, fs);
+    }
     const double ds = dS_fp64<Q>(fd, fs);
     if (ds > g.delta) {
       const uint32_t idx = atomicAdd(&a.ctr[C_CAND], 1u);
@@ -367,11 +392,15 @@ __global__ __launch_bounds__(64) void k_reset(StepArgs a) {
   const Geom& g = a.g;
   const uint32_t site = a.sel[t];
   const int64_t y = site / g.nx, x = site - y * g.nx;
-  T f[Q];
-  load_site<T, Q, PULL>(A, g, x, y, f);
-  const Moments<Q, T> m = moments<Q, T>(f);
   T fs[Q];
-  qe_eval<Q, QE, T>(m, fs);
+  if constexpr (QE == QE_ENTROPIC_M) {
+    fstar_from_mu_buf<T>(a.mu, g.nx * g.ny, site, fs);
+  } else {
+    T f[Q];
+    load_site<T, Q, PULL>(A, g, x, y, f);
+    const Moments<Q, T> m = moments<Q, T>(f);
+    qe_eval<Q, QE, T>(m, fs);
+  }
   const int64_t o = y * g.pitch + x;
   #pragma unroll
   for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = fs[i];
@@ -464,12 +493,47 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, double* __restrict_
   }
 }
 
-// fixed-order reduction of the block partials of the last step
-__global__ __launch_bounds__(256) void k_finalize(StepArgs a) {
+// FP64 sums over fluid sites of rho, rho u1, rho u2, 2E of the current
+// pre-collision state (the conservation diagnostics): per-thread sums in a
+// fixed grid-stride order, per-block partials, then one block in fixed order
+constexpr int SUM_BLOCKS = 1024;
+
+template <typename T, int Q, bool PULL>
+__global__ __launch_bounds__(256) void k_sums(StepArgs a) {
+  const T* __restrict__ A = (const T*)a.A;
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const int64_t y = i / g.nx, x = i - y * g.nx;
+    if (is_solid(g, x, y)) continue;
+    T f[Q];
+    load_site<T, Q, PULL>(A, g, x, y, f);
+    double fd[Q];
+    #pragma unroll
+    for (int q = 0; q < Q; ++q) fd[q] = (double)f[q];
+    const Moments<Q, double> m = moments<Q, double>(fd);
+    s[0] += m.rho;
+    s[1] += m.jx;
+    s[2] += m.jy;
+    s[3] += m.e2;
+  }
+  __shared__ double red[4][256];
+  for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) a.partials[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_finalize(StepArgs a, int nb) {
   __shared__ double red[4][256];
   const int tid = threadIdx.x;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t b = tid; b < a.nblocks; b += 256)
+  for (int b = tid; b < nb; b += 256)
     for (int c = 0; c < 4; ++c) s[c] += a.partials[b * 4 + c];
   for (int c = 0; c < 4; ++c) red[c][tid] = s[c];
   __syncthreads();
@@ -484,12 +548,77 @@ __global__ __launch_bounds__(256) void k_finalize(StepArgs a) {
 __global__ __launch_bounds__(256) void k_clear(StepArgs a) {
   const int64_t t0 = blockIdx.x * 256ll + threadIdx.x, stride = (int64_t)gridDim.x * 256;
   for (int64_t j = t0; j < HIST_BINS; j += stride) a.hist[j] = 0;
-  for (int64_t j = t0; j < a.nblocks * 4; j += stride) a.partials[j] = 0.0;
+  for (int64_t j = t0; j < SUM_BLOCKS * 4; j += stride) a.partials[j] = 0.0;
   if (t0 < C_COUNT) a.ctr[t0] = 0;
   if (t0 == 0) {
     a.st->n_above = a.st->n_sel = a.st->n_invalid = a.st->total_sel = 0;
     a.st->kth = a.st->max = 0.0;
     for (int c = 0; c < 4; ++c) a.st->sums[c] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// f*_M support: moments for the solver, initial state from the multipliers
+// ---------------------------------------------------------------------------
+template <typename T, bool PULL>
+__global__ __launch_bounds__(256) void k_moments_M(StepArgs a) {
+  const T* __restrict__ A = (const T*)a.A;
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    const int64_t y = s / g.nx, x = s - y * g.nx;
+    double r = 1.0, jx = 0.0, jy = 0.0, e2 = 2.0 / 3.0;
+    if (!is_solid(g, x, y)) {
+      T f[9];
+      load_site<T, 9, PULL>(A, g, x, y, f);
+      double fd[9];
+      #pragma unroll
+      for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
+      const Moments<9, double> m = moments<9, double>(fd);
+      r = m.rho;
+      jx = m.jx;
+      jy = m.jy;
+      e2 = m.e2;
+    }
+    a.Mbuf[s] = r;
+    a.Mbuf[N + s] = jx;
+    a.Mbuf[2 * N + s] = jy;
+    a.Mbuf[3 * N + s] = e2;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_init_M_moments(StepArgs a, const double* __restrict__ rho0,
+                                                        const double* __restrict__ u0,
+                                                        const double* __restrict__ twoE0) {
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    const int64_t y = s / g.nx, x = s - y * g.nx;
+    const bool sol = is_solid(g, x, y);
+    const double r = sol ? 1.0 : rho0[s];
+    a.Mbuf[s] = r;
+    a.Mbuf[N + s] = sol ? 0.0 : r * u0[s];
+    a.Mbuf[2 * N + s] = sol ? 0.0 : r * u0[N + s];
+    a.Mbuf[3 * N + s] = sol ? 2.0 / 3.0 : r * twoE0[s];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_M_pops(StepArgs a) {
+  T* __restrict__ S = (T*)a.B;
+  const Geom& g = a.g;
+  const int64_t N = g.nx * g.ny;
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
+    const int64_t y = s / g.nx, x = s - y * g.nx;
+    double fs[9];
+    if (is_solid(g, x, y)) {
+      #pragma unroll
+      for (int i = 0; i < 9; ++i) fs[i] = 0.0;
+    } else {
+      fstar_pop<double>(::exp(a.mu[s]), ::exp(a.mu[N + s]), ::exp(a.mu[2 * N + s]), ::exp(a.mu[3 * N + s]), fs);
+    }
+    #pragma unroll
+    for (int i = 0; i < 9; ++i) S[(int64_t)i * g.plane + y * g.pitch + x] = (T)fs[i];
   }
 }
 
@@ -517,8 +646,10 @@ static hipError_t step_p(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t
 
 template <typename T, int Q>
 static hipError_t step_q(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  return a.qe == QE_POLY ? step_p<T, Q, QE_POLY>(a, pull, s, e0, e1)
-                         : step_p<T, Q, QE_ENTROPIC_MM>(a, pull, s, e0, e1);
+  if (a.qe == QE_POLY) return step_p<T, Q, QE_POLY>(a, pull, s, e0, e1);
+  if (a.qe == QE_ENTROPIC_MM) return step_p<T, Q, QE_ENTROPIC_MM>(a, pull, s, e0, e1);
+  if constexpr (Q == 9) return step_p<T, 9, QE_ENTROPIC_M>(a, pull, s, e0, e1);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -591,13 +722,45 @@ hipError_t launch_moments(const StepArgs& a, bool pull, double* rho, double* rho
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
+template <typename T, int Q>
+static void sums_t(const StepArgs& a, bool pull, hipStream_t s) {
+  if (pull) hipLaunchKernelGGL((k_sums<T, Q, true>), dim3(SUM_BLOCKS), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_sums<T, Q, false>), dim3(SUM_BLOCKS), dim3(256), 0, s, a);
+}
+
+hipError_t launch_sums(const StepArgs& a, bool pull, hipStream_t s) {
+  if (a.prec == 1) { if (a.Q == 9) sums_t<double, 9>(a, pull, s); else sums_t<double, 3>(a, pull, s); }
+  else { if (a.Q == 9) sums_t<float, 9>(a, pull, s); else sums_t<float, 3>(a, pull, s); }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a, SUM_BLOCKS);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s) {
+  const unsigned gr = site_grid(a);
+  if (a.prec == 1) {
+    if (pull) hipLaunchKernelGGL((k_moments_M<double, true>), dim3(gr), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_moments_M<double, false>), dim3(gr), dim3(256), 0, s, a);
+  } else {
+    if (pull) hipLaunchKernelGGL((k_moments_M<float, true>), dim3(gr), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_moments_M<float, false>), dim3(gr), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_M_moments(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_init_M_moments, dim3(site_grid(a)), dim3(256), 0, s, a, rho0, u0, twoE0);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_M_pops(const StepArgs& a, hipStream_t s) {
+  if (a.prec == 1) hipLaunchKernelGGL((k_init_M_pops<double>), dim3(site_grid(a)), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_init_M_pops<float>), dim3(site_grid(a)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_clear(const StepArgs& a, hipStream_t s) {
-  int64_t n = a.nblocks * 4 > HIST_BINS ? a.nblocks * 4 : HIST_BINS;
+  int64_t n = HIST_BINS;
   int64_t nb = (n + 255) / 256;
   hipLaunchKernelGGL(k_clear, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, a);
   return hipGetLastError();

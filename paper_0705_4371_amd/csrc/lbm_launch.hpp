@@ -49,7 +49,9 @@ struct StepArgs {
   uint32_t* sel;
   double* sel_ds;
   DevStats* st;
-  double* partials;
+  double* partials;  // [1024][4] FP64 block partials of the conservation sums
+  double* Mbuf;      // f*_M only: moments [4][N] of the current step
+  const double* mu;  // f*_M only: multipliers [4][N] of the current step
   float thr_a, thr_b;  // FP32 screen threshold: thr_a - thr_b * sqrt(rho)
   int64_t ntx, nblocks;
   int prec, Q, qe;
@@ -61,11 +63,20 @@ hipError_t launch_step(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t e
 
 hipError_t launch_init(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,
                        hipStream_t s);
+// f*_M: moments of the current pre-collision state into a.Mbuf (solid sites
+// get the isothermal rest moments so that the solver has a feasible input)
+hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s);
+// f*_M initial state: moments of the initial fields into a.Mbuf, and (after
+// the solve) f = f*(mu) into the state buffer a.B
+hipError_t launch_init_M_moments(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,
+                                 hipStream_t s);
+hipError_t launch_init_M_pops(const StepArgs& a, hipStream_t s);
 hipError_t launch_get(const StepArgs& a, bool pull, void* out, hipStream_t s);
 hipError_t launch_set(const StepArgs& a, const void* in, hipStream_t s);
 hipError_t launch_moments(const StepArgs& a, bool pull, double* rho, double* rhou, double* e2,
                           hipStream_t s);
-hipError_t launch_finalize(const StepArgs& a, hipStream_t s);
+// FP64 conservation sums of the current pre-collision state into st->sums
+hipError_t launch_sums(const StepArgs& a, bool pull, hipStream_t s);
 hipError_t launch_clear(const StepArgs& a, hipStream_t s);
 
 }  // namespace lbm

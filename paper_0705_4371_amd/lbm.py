@@ -43,7 +43,7 @@ class lbm_es_stats(C.Structure):
     _fields_ = [
         ("step", C.c_int64), ("n_above_delta", C.c_int64), ("n_selected", C.c_int64),
         ("n_invalid", C.c_int64), ("n_fallback", C.c_int64), ("total_selected", C.c_int64),
-        ("nonfinite", C.c_int64), ("pad0", C.c_int64),
+        ("nonfinite", C.c_int64), ("newton_updates", C.c_int64),
         ("kth_dS", C.c_double), ("max_dS", C.c_double), ("mass", C.c_double),
         ("mom", C.c_double * 2), ("energy", C.c_double),
     ]
@@ -146,13 +146,17 @@ def make_config(lattice=LBM_D2Q9, qe=LBM_QE_POLY, precision=LBM_FP32, nx=64, ny=
     return c
 
 
-def config_from_workload(d: dict, precision: int, stream=None) -> lbm_config:
+def config_from_workload(d: dict, precision: int, stream=None, fstar_start=LBM_START_DEFAULT,
+                         net=None) -> lbm_config:
     """Config from a workloads.* parameter dict (keys Q, qe, nx, ny, nu, ...)."""
-    return make_config(lattice=d["Q"], qe=d.get("qe", LBM_QE_POLY), precision=precision,
-                       nx=d["nx"], ny=d["ny"], nu=d["nu"], delta=d.get("delta", math.inf),
-                       k=d.get("k", 0), bc=d.get("bc", (LBM_BC_PERIODIC,) * 4),
-                       inlet_rho=d.get("inlet_rho", 1.0), inlet_u=d.get("inlet_u", (0.0, 0.0)),
-                       solid=d.get("solid", (0, 0, 0, 0)), stream=stream)
+    c = make_config(lattice=d["Q"], qe=d.get("qe", LBM_QE_POLY), precision=precision,
+                    nx=d["nx"], ny=d["ny"], nu=d["nu"], delta=d.get("delta", math.inf),
+                    k=d.get("k", 0), bc=d.get("bc", (LBM_BC_PERIODIC,) * 4),
+                    inlet_rho=d.get("inlet_rho", 1.0), inlet_u=d.get("inlet_u", (0.0, 0.0)),
+                    solid=d.get("solid", (0, 0, 0, 0)), fstar_start=fstar_start, stream=stream)
+    if net is not None:
+        c.net = net.h
+    return c
 
 
 class Lattice:
