@@ -72,6 +72,118 @@ def cpu_baseline(args):
                       % (args.cpu_nx, args.cpu_rows, args.cpu_steps, dt)}
 
 
+def cylinder_leg(args, torch, lbm, W, net):
+    """Flow past the square cylinder on 2400 x 800 at Re = 20000 with the
+    entropic f*_M quasiequilibrium in every step (per-site Newton, plain-Newton
+    fallback) and Ehrenfests' steps (delta = 1e-3, k = 256), from the rest
+    start and from the trained network start."""
+    d, rho, u = W.CONFIGS["cylinder_2400x800_re20000_fstarM"]()
+    e0 = W.iso_energy(u[0], u[1])
+    out = {"lattice": "%dx%d" % (d["nx"], d["ny"]), "steps": args.cyl_steps}
+    for name, start in (("rest", lbm.LBM_START_DEFAULT), ("mlp", lbm.LBM_START_MLP)):
+        cfg = lbm.config_from_workload(d, lbm.LBM_FP32, fstar_start=start,
+                                       net=net if start == lbm.LBM_START_MLP else None)
+        lat = lbm.Lattice(cfg, rho, u, e0)
+        lat.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fb = 0
+        upd = 0
+        sel = 0
+        above = 0
+        chunk = 100
+        for _ in range(args.cyl_steps // chunk):
+            lat.step(chunk)
+            st, _, _ = lat.stats()
+            fb += st.n_fallback
+            upd += st.newton_updates
+            above += st.n_above_delta
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st, _, ds = lat.stats(sel_cap=256)
+        fluid = d["nx"] * d["ny"] - d["solid"][2] * d["solid"][3]
+        out[name] = {"MLUPS": round(fluid * args.cyl_steps / dt / 1e6, 1),
+                     "ms_per_step": round(dt * 1e3 / args.cyl_steps, 4),
+                     "fallback_sites_sampled_steps": int(fb),
+                     "fallback_rate": fb / (fluid * (args.cyl_steps // chunk)),
+                     "newton_updates_per_site": upd / (fluid * (args.cyl_steps // chunk)),
+                     "last_step": {"n_above_delta": st.n_above_delta, "n_selected": st.n_selected,
+                                   "max_dS": st.max_dS, "kth_dS": st.kth_dS, "nonfinite": st.nonfinite},
+                     "selected_total": st.total_selected, "mass": st.mass, "energy": st.energy}
+        lat.close()
+    return out
+
+
+def fstar_leg(args, torch, lbm, W):
+    """Entropic f*_M solve on the 4096 x 2048 moment field: the warm-start MLP
+    is trained on 2^24 (moments, multipliers) pairs produced by the solver
+    (batch 65536, 20 epochs, Adam 1e-3), then the solve is timed from the rest
+    start, the closed-form start and the network start, each to a residual
+    <= 1e-10 (plain Newton fallback enabled)."""
+    import numpy as np
+    out = {}
+    # training pairs: moments of the study's distribution, multipliers by the solver
+    npairs = 1 << args.pairs_log2
+    Mtr = torch.from_numpy(W.random_moments(npairs, 5)).cuda()
+    solver = lbm.FstarSolver(max(npairs, args.fx * args.fy))
+    mu_tr, _, _, st = solver.solve(Mtr, start=lbm.LBM_START_DEFAULT)
+    net = lbm.Mlp(5)
+    ish, isc, osh, osc = W.mlp_norm()
+    net.set_norm(ish, isc, osh, osc)
+    f64 = torch.float64
+    ish_t, isc_t = torch.tensor(ish, dtype=f64, device="cuda"), torch.tensor(isc, dtype=f64, device="cuda")
+    osh_t, osc_t = torch.tensor(osh, dtype=f64, device="cuda"), torch.tensor(osc, dtype=f64, device="cuda")
+    u1, u2, e = Mtr[1] / Mtr[0], Mtr[2] / Mtr[0], Mtr[3] / Mtr[0]
+    X = ((torch.stack([u1, u2, e, u1 * u1 + u2 * u2], 1) - ish_t) * isc_t).float().contiguous()
+    T = ((torch.stack([mu_tr[0] - torch.log(Mtr[0]), mu_tr[1], mu_tr[2], mu_tr[3]], 1) - osh_t) * osc_t).float().contiguous()
+    del Mtr, mu_tr
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(X, T, epochs=args.epochs, batch=args.batch, lr=1e-3, seed=5)
+    torch.cuda.synchronize()
+    out["training"] = {"pairs": npairs, "epochs": args.epochs, "batch": args.batch,
+                       "adam_steps": args.epochs * (npairs // args.batch),
+                       "seconds": round(time.perf_counter() - t0, 3),
+                       "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}
+    del X, T
+    # the timed solves
+    M = torch.from_numpy(W.moment_field(nx=args.fx, ny=args.fy)).cuda()
+    n = M.shape[1]
+    mu = torch.empty_like(M)
+    it = torch.empty(n, dtype=torch.uint8, device="cuda")
+    stt = torch.empty(n, dtype=torch.uint8, device="cuda")
+    res = {}
+    for name, start in (("rest", lbm.LBM_START_DEFAULT), ("closed_form", lbm.LBM_START_CLOSED_FORM),
+                        ("mlp", lbm.LBM_START_MLP)):
+        kw = dict(start=start, net=net if start == lbm.LBM_START_MLP else None, mu=mu, iters=it, status=stt)
+        _, _, _, st = solver.solve(M, stats=True, **kw)          # statistics (synchronising)
+        for _ in range(3):
+            solver.solve(M, stats=False, **kw)                    # warm-up
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        reps = 20
+        for _ in range(reps):
+            solver.solve(M, stats=False, **kw)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        res[name] = {"ms": round(ms, 4), "Msites_per_s": round(n / ms / 1e3, 1),
+                     "mean_newton_updates": round(st.mean_fp32_iters + st.mean_fp64_iters, 4),
+                     "mean_fp32": round(st.mean_fp32_iters, 4), "mean_fp64": round(st.mean_fp64_iters, 4),
+                     "fallback": int(st.n_fallback), "failed": int(st.n_failed),
+                     "max_residual": st.max_resid}
+    out["sites"] = n
+    out["solve"] = res
+    if not args.no_cylinder:
+        out["cylinder_fstarM"] = cylinder_leg(args, torch, lbm, W, net)
+    out["speedup_mlp_vs_rest"] = round(res["rest"]["ms"] / res["mlp"]["ms"], 3)
+    out["speedup_closed_form_vs_rest"] = round(res["rest"]["ms"] / res["closed_form"]["ms"], 3)
+    solver.close()
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +196,14 @@ def main():
     ap.add_argument("--cpu-nx", type=int, default=8192)
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-fstar", action="store_true", help="skip the f*_M / MLP leg")
+    ap.add_argument("--no-cylinder", action="store_true", help="skip the f*_M cylinder run")
+    ap.add_argument("--cyl-steps", type=int, default=2000)
+    ap.add_argument("--fx", type=int, default=4096)
+    ap.add_argument("--fy", type=int, default=2048)
+    ap.add_argument("--pairs-log2", type=int, default=24)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB float32 tensor 10 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -178,6 +298,9 @@ def main():
         "graph_replay_MLUPS": round(n_sites * args.steps / dt_graph / 1e6, 1),
     }
     lat.close()
+    if not args.no_fstar:
+        print("# f*_M leg", file=sys.stderr, flush=True)
+        out["fstar"] = fstar_leg(args, torch, lbm, W)
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args)

@@ -142,7 +142,6 @@ void lbm_mlp_free(lbm_mlp* net) {
   float* ptrs[] = {net->params, net->m, net->v, net->grad, net->partials, net->loss};
   for (float* p : ptrs)
     if (p) (void)hipFree(p);
-  if (net->idx) (void)hipFree(net->idx);
   delete net;
 }
 
@@ -156,7 +155,7 @@ int lbm_mlp_create(uint64_t seed, lbm_mlp** out) {
   const size_t pb = sizeof(float) * MLP_NPARAM;
   bool ok = hipMalloc((void**)&net->params, pb) == hipSuccess && hipMalloc((void**)&net->m, pb) == hipSuccess &&
             hipMalloc((void**)&net->v, pb) == hipSuccess && hipMalloc((void**)&net->grad, pb) == hipSuccess &&
-            hipMalloc((void**)&net->partials, sizeof(float) * 256 * (MLP_NPARAM + 1)) == hipSuccess;
+            hipMalloc((void**)&net->partials, sizeof(float) * MLP_GRAD_MAX_BLOCKS * (MLP_NPARAM + 1)) == hipSuccess;
   if (!ok) {
     lbm_mlp_free(net);
     return lbm_internal_fail(LBM_E_NOMEM, "network allocation failed");
@@ -241,7 +240,8 @@ int lbm_mlp_loss_grad(lbm_mlp* net, const float* X, const float* T, int64_t n, f
                       void* stream) {
   if (!net || !X || !T || !grad || n < 1) return lbm_internal_fail(LBM_E_INVAL, "net, X, T, grad and n >= 1 are required");
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(launch_mlp_grad(net->params, X, T, n, nullptr, net->partials, s));
+  MlpPerm ident{};
+  HIPCHK(launch_mlp_grad(net->params, X, T, n, ident, net->partials, s));
   HIPCHK(launch_mlp_reduce(net->partials, mlp_grad_blocks(n), n, grad, loss, s));
   return LBM_OK;
 }
@@ -260,13 +260,6 @@ int lbm_mlp_train(lbm_mlp* net, const float* X, const float* T, int64_t n, int32
     return lbm_internal_fail(LBM_E_INVAL, "need 1 <= batch <= n < 2^31, epochs >= 0, lr > 0");
   hipStream_t s = (hipStream_t)stream;
   const int64_t nb = n / batch;  // full batches per epoch; the remainder is dropped
-  if (net->idx_cap < n) {
-    if (net->idx) HIPCHK(hipFree(net->idx));
-    net->idx = nullptr;
-    if (hipMalloc((void**)&net->idx, sizeof(int32_t) * (size_t)n) != hipSuccess)
-      return lbm_internal_fail(LBM_E_NOMEM, "index buffer allocation failed");
-    net->idx_cap = n;
-  }
   if (net->loss_cap < nb) {
     if (net->loss) HIPCHK(hipFree(net->loss));
     net->loss = nullptr;
@@ -274,22 +267,19 @@ int lbm_mlp_train(lbm_mlp* net, const float* X, const float* T, int64_t n, int32
       return lbm_internal_fail(LBM_E_NOMEM, "loss buffer allocation failed");
     net->loss_cap = nb;
   }
-  std::vector<int32_t> perm((size_t)n);
   std::vector<float> lb((size_t)nb);
+  int bits = 0;
+  while (((int64_t)1 << bits) < n) ++bits;
+  MlpPerm perm{};
+  perm.on = 1;
+  perm.h = (bits + 1) / 2 > 0 ? (bits + 1) / 2 : 1;
+  perm.n = (uint32_t)n;
   for (int32_t ep = 0; ep < epochs; ++ep) {
-    // Fisher-Yates shuffle driven by SplitMix64 on (seed, epoch, position)
-    for (int64_t i = 0; i < n; ++i) perm[(size_t)i] = (int32_t)i;
-    const uint64_t es = splitmix64(shuffle_seed ^ ((uint64_t)ep << 40));
-    for (int64_t i = n - 1; i > 0; --i) {
-      const int64_t j = (int64_t)(u01(es, (uint64_t)i) * (double)(i + 1));
-      const int32_t tmp = perm[(size_t)i];
-      perm[(size_t)i] = perm[(size_t)(j <= i ? j : i)];
-      perm[(size_t)(j <= i ? j : i)] = tmp;
-    }
-    HIPCHK(hipStreamSynchronize(s));  // the previous epoch still reads idx
-    HIPCHK(hipMemcpyAsync(net->idx, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    // a fresh pseudo-random order of the n samples every epoch
+    perm.key = splitmix64(shuffle_seed ^ ((uint64_t)(ep + 1) << 32));
     for (int64_t b = 0; b < nb; ++b) {
-      HIPCHK(launch_mlp_grad(net->params, X, T, batch, net->idx + b * batch, net->partials, s));
+      perm.offset = (uint32_t)(b * batch);
+      HIPCHK(launch_mlp_grad(net->params, X, T, batch, perm, net->partials, s));
       HIPCHK(launch_mlp_reduce(net->partials, mlp_grad_blocks(batch), batch, net->grad, net->loss + b, s));
       net->t++;
       HIPCHK(launch_adam(net->params, net->m, net->v, net->grad, net->t, (float)lr, 0.9f, 0.999f, 1e-8f, s));

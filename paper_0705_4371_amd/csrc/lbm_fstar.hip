@@ -69,22 +69,16 @@ __device__ __forceinline__ void write_mu(double* mu, int64_t n, int64_t i, doubl
   mu[3 * n + i] = ::log(s.Z);
 }
 
-// block-aggregated statistics
+// Statistics are accumulated per thread over its sites, reduced per
+// wavefront with shuffles and per block in LDS, and added to the global
+// counters once per block (the grid is capped so that these atomics stay few).
 struct SolveAcc {
   uint32_t hist[16];
-  uint32_t sum32, sum64, infeasible, fail;
+  uint32_t sum32, sum64, infeasible, pad;
   unsigned long long maxres_bits;
 };
 
-__device__ __forceinline__ void acc_add(SolveAcc* sh, int it32, int it64, bool infeas, bool fail, double res) {
-  const int tot = it32 + it64;
-  atomicAdd(&sh->hist[tot < 15 ? tot : 15], 1u);
-  atomicAdd(&sh->sum32, (uint32_t)it32);
-  atomicAdd(&sh->sum64, (uint32_t)it64);
-  if (infeas) atomicAdd(&sh->infeasible, 1u);
-  if (fail) atomicAdd(&sh->fail, 1u);
-  if (!infeas && !fail) atomicMax(&sh->maxres_bits, (unsigned long long)__double_as_longlong(res));
-}
+constexpr int FSTAR_MAX_BLOCKS = 2048;
 
 template <int START>
 __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
@@ -92,83 +86,116 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
   if (threadIdx.x < sizeof(SolveAcc) / 4) ((uint32_t*)&sh)[threadIdx.x] = 0;
   __syncthreads();
   const int64_t n = a.n;
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
-  if (i < n) {
-    const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
+  const int lane = threadIdx.x & 63;
+  uint32_t sum32 = 0, sum64 = 0, ninf = 0;
+  double maxres = 0.0;
+  // the trip count is uniform across the block so that every lane takes part
+  // in the wavefront-level histogram below
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t base = blockIdx.x * 256ll; base < n; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    const bool live = i < n;
     int it32 = 0, it64 = 0;
-    bool infeas = false, fail = false;
-    double res = 0.0;
-    if (!feasible(rho, u1, u2, e)) {
-      infeas = true;
-      if (__builtin_fabs(u1) < 1.0 && __builtin_fabs(u2) < 1.0 && rho > 0.0) {
-        write_mu(a.mu, n, i, rho, closed_form<double>(u1, u2));
-      } else {
-        for (int c = 0; c < 4; ++c) a.mu[c * n + i] = __builtin_nan("");
-      }
-      if (a.status) a.status[i] = 2;
-    } else {
-      // ---- FP32 phase
-      FS<float> s;
-      if (START == START_CLOSED) {
-        s = closed_form<float>((float)u1, (float)u2);
-      } else if (START == START_WARM) {
-        s.a = __expf(a.warm[i]);
-        s.X = __expf(a.warm[n + i]);
-        s.Y = __expf(a.warm[2 * n + i]);
-        s.Z = __expf(a.warm[3 * n + i]);
-      } else {
-        s.a = 4.0f / 9.0f;
-        s.X = 1.0f;
-        s.Y = 1.0f;
-        s.Z = 0.25f;
-      }
-      const float fu1 = (float)u1, fu2 = (float)u2, fe = (float)e;
-      float g[4], H[10], d[4];
-      float prev = 3.0e38f;
-      for (;;) {
-        fsys<float>(s, fu1, fu2, fe, g, H);
-        const float r = resid(g);
-        if (!(r > a.tol32) || it32 >= a.max32 || !(r < 0.25f * prev)) break;
-        prev = r;
-        fsolve<float>(H, g, d);
-        float dm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
-        const float sc = dm > 1.0f ? 1.0f / dm : 1.0f;
-        s.a *= __expf(sc * d[0]);
-        s.X *= __expf(sc * d[1]);
-        s.Y *= __expf(sc * d[2]);
-        s.Z *= __expf(sc * d[3]);
-        ++it32;
-      }
-      // ---- FP64 phase
-      FS<double> t{(double)s.a, (double)s.X, (double)s.Y, (double)s.Z};
-      bool ok = false;
-      if (__builtin_isfinite(t.a) && t.a > 0.0 && t.X > 0.0 && t.Y > 0.0 && t.Z > 0.0 &&
-          __builtin_isfinite(t.X) && __builtin_isfinite(t.Y) && __builtin_isfinite(t.Z)) {
-        double gd[4], Hd[10], dd[4];
-        for (;;) {
-          fsys<double>(t, u1, u2, e, gd, Hd);
-          res = resid(gd);
-          if (res <= a.tol) { ok = true; break; }
-          if (it64 >= a.max64 || !(res < 1e-2)) break;
-          fsolve<double>(Hd, gd, dd);
-          t.a *= exp_step(dd[0]);
-          t.X *= exp_step(dd[1]);
-          t.Y *= exp_step(dd[2]);
-          t.Z *= exp_step(dd[3]);
-          ++it64;
+    if (live) {
+      const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
+      double res = 0.0;
+      if (!feasible(rho, u1, u2, e)) {
+        ninf++;
+        if (__builtin_fabs(u1) < 1.0 && __builtin_fabs(u2) < 1.0 && rho > 0.0) {
+          write_mu(a.mu, n, i, rho, closed_form<double>(u1, u2));
+        } else {
+          for (int c = 0; c < 4; ++c) a.mu[c * n + i] = __builtin_nan("");
         }
-      }
-      if (ok) {
-        write_mu(a.mu, n, i, rho, t);
-        if (a.status) a.status[i] = 0;
+        if (a.status) a.status[i] = 2;
       } else {
-        fail = true;
-        const uint32_t slot = atomicAdd(&a.ctr[0], 1u);
-        a.fail_list[slot] = (uint32_t)i;
+        // ---- FP32 phase
+        FS<float> s;
+        if (START == START_CLOSED) {
+          s = closed_form<float>((float)u1, (float)u2);
+        } else if (START == START_WARM) {
+          s.a = __expf(a.warm[i]);
+          s.X = __expf(a.warm[n + i]);
+          s.Y = __expf(a.warm[2 * n + i]);
+          s.Z = __expf(a.warm[3 * n + i]);
+        } else {
+          s.a = 4.0f / 9.0f;
+          s.X = 1.0f;
+          s.Y = 1.0f;
+          s.Z = 0.25f;
+        }
+        const float fu1 = (float)u1, fu2 = (float)u2, fe = (float)e;
+        float g[4], H[10], d[4];
+        float prev = 3.0e38f;
+        for (;;) {
+          fsys<float>(s, fu1, fu2, fe, g, H);
+          const float r = resid(g);
+          if (!(r > a.tol32) || it32 >= a.max32 || !(r < 0.25f * prev)) break;
+          prev = r;
+          fsolve<float>(H, g, d);
+          float dm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
+          const float sc = dm > 1.0f ? 1.0f / dm : 1.0f;
+          s.a *= __expf(sc * d[0]);
+          s.X *= __expf(sc * d[1]);
+          s.Y *= __expf(sc * d[2]);
+          s.Z *= __expf(sc * d[3]);
+          ++it32;
+        }
+        // ---- FP64 phase
+        FS<double> t{(double)s.a, (double)s.X, (double)s.Y, (double)s.Z};
+        bool ok = false;
+        if (__builtin_isfinite(t.a) && t.a > 0.0 && t.X > 0.0 && t.Y > 0.0 && t.Z > 0.0 &&
+            __builtin_isfinite(t.X) && __builtin_isfinite(t.Y) && __builtin_isfinite(t.Z)) {
+          double gd[4], Hd[10], dd[4];
+          for (;;) {
+            fsys<double>(t, u1, u2, e, gd, Hd);
+            res = resid(gd);
+            if (res <= a.tol) { ok = true; break; }
+            if (it64 >= a.max64 || !(res < 1e-2)) break;
+            fsolve<double>(Hd, gd, dd);
+            t.a *= exp_step(dd[0]);
+            t.X *= exp_step(dd[1]);
+            t.Y *= exp_step(dd[2]);
+            t.Z *= exp_step(dd[3]);
+            ++it64;
+          }
+        }
+        if (ok) {
+          write_mu(a.mu, n, i, rho, t);
+          if (a.status) a.status[i] = 0;
+          maxres = fmax(maxres, res);
+        } else {
+          const uint32_t slot = atomicAdd(&a.ctr[0], 1u);
+          a.fail_list[slot] = (uint32_t)i;
+        }
+        sum32 += (uint32_t)it32;
+        sum64 += (uint32_t)it64;
       }
+      if (a.iters) a.iters[i] = (uint8_t)(it32 + it64 < 255 ? it32 + it64 : 255);
     }
-    if (a.iters) a.iters[i] = (uint8_t)(it32 + it64 < 255 ? it32 + it64 : 255);
-    acc_add(&sh, it32, it64, infeas, fail, res);
+    // histogram of updates: one pass per distinct value in the wavefront
+    const int tot = it32 + it64 < 15 ? it32 + it64 : 15;
+    unsigned long long rem = __ballot(live);
+    while (rem) {
+      const int src = __ffsll((long long)rem) - 1;
+      const int b = __shfl(tot, src);
+      const unsigned long long m = __ballot(live && tot == b);
+      if (lane == 0) atomicAdd(&sh.hist[b], (uint32_t)__popcll(m));
+      rem &= ~m;
+    }
+  }
+  // wavefront reductions, then one LDS atomic per wavefront
+  #pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sum32 += __shfl_xor(sum32, off);
+    sum64 += __shfl_xor(sum64, off);
+    ninf += __shfl_xor(ninf, off);
+    maxres = fmax(maxres, __shfl_xor(maxres, off));
+  }
+  if (lane == 0) {
+    atomicAdd(&sh.sum32, sum32);
+    atomicAdd(&sh.sum64, sum64);
+    atomicAdd(&sh.infeasible, ninf);
+    atomicMax(&sh.maxres_bits, (unsigned long long)__double_as_longlong(maxres));
   }
   __syncthreads();
   if (threadIdx.x < 16 && sh.hist[threadIdx.x]) atomicAdd(&a.stats->hist[threadIdx.x], (unsigned long long)sh.hist[threadIdx.x]);
@@ -211,7 +238,8 @@ __global__ void k_fstar_clear(FstarArgs a) {
 
 hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s) {
   hipLaunchKernelGGL(k_fstar_clear, dim3(1), dim3(64), 0, s, a);
-  const unsigned nb = (unsigned)((a.n + 255) / 256);
+  int64_t nb64 = (a.n + 255) / 256;
+  const unsigned nb = (unsigned)(nb64 < FSTAR_MAX_BLOCKS ? nb64 : FSTAR_MAX_BLOCKS);
   if (nb > 0) {
     if (start == START_CLOSED) hipLaunchKernelGGL((k_fstar<START_CLOSED>), dim3(nb), dim3(256), 0, s, a);
     else if (start == START_WARM) hipLaunchKernelGGL((k_fstar<START_WARM>), dim3(nb), dim3(256), 0, s, a);

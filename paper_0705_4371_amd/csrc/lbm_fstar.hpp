@@ -49,11 +49,21 @@ hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n, fl
 // (mu0 - ln rho, mu1, mu2, mu3) into warm[4][n]
 hipError_t launch_mlp_warm(const float* params, const MlpNorm& nm, const double* M, int64_t n, float* warm,
                            hipStream_t s);
+// sample order of a training epoch: position offset + s reads sample
+// perm(offset + s) of the n_total samples (on == 0: identity)
+struct MlpPerm {
+  int on;
+  int h;            // half width in bits of the Feistel domain (2h >= log2 n_total)
+  uint32_t n;       // n_total
+  uint32_t offset;  // first position of this batch
+  uint64_t key;     // epoch key
+};
+constexpr int MLP_GRAD_MAX_BLOCKS = 1024;
 // per-block gradient partials of the MSE loss over n samples; returns the
 // number of blocks used (partials is [nblocks][MLP_NPARAM + 1], the last
 // column the block's loss sum)
 int mlp_grad_blocks(int64_t n);
-hipError_t launch_mlp_grad(const float* params, const float* X, const float* T, int64_t n, const int32_t* idx,
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* T, int64_t n, const MlpPerm& perm,
                            float* partials, hipStream_t s);
 // reduce partials (fixed order), Adam update of params (FP32 master), m, v
 hipError_t launch_mlp_reduce(const float* partials, int nblocks, int64_t n, float* grad, float* loss,

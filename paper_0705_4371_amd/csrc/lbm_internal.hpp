@@ -26,11 +26,9 @@ struct lbm_mlp {
   float* m = nullptr;
   float* v = nullptr;
   float* grad = nullptr;
-  float* partials = nullptr;  // [256][4741]
+  float* partials = nullptr;  // [MLP_GRAD_MAX_BLOCKS][4741]
   float* loss = nullptr;      // per-batch losses of the current epoch
   int64_t loss_cap = 0;
-  int32_t* idx = nullptr;
-  int64_t idx_cap = 0;
   int64_t t = 0;  // Adam step
   lbm::MlpNorm norm{};
 };

@@ -28,9 +28,13 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU z sigma(z) and its derivative sigma(z)(1 + z(1 - sigma(z))) in FP32;
+// the hardware reciprocal (1 ulp) is ample: the activation is rounded to
+// BF16 (8 bits) before its next use
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigm(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -78,6 +82,35 @@ __device__ void load_weights(const float* __restrict__ p, int r, int g, Weights&
   for (int kk = 0; kk < 2; ++kk) w.w3[kk] = r < 4 ? load8(p + MLP_OW3 + r * 64 + 32 * kk + 8 * g) : zero8();
   #pragma unroll
   for (int j = 0; j < 4; ++j) w.b3[j] = g == 0 ? p[MLP_OB3 + j] : 0.0f;
+}
+
+// Epoch shuffle: position i of the epoch reads sample perm(i), perm a
+// pseudo-random bijection of [0, n): a 4-round Feistel network on 2h bits
+// (2h >= log2 n, round function SplitMix64 of (key, round, half)) with
+// cycle-walking into [0, n).  Walking the cycle of a bijection returns to a
+// value below n (at worst to i itself), so the loop terminates.
+__device__ __forceinline__ uint64_t smix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ uint32_t feistel_perm(uint32_t i, const MlpPerm& p) {
+  const uint32_t mask = (1u << p.h) - 1u;
+  uint32_t x = i;
+  do {
+    uint32_t L = x >> p.h, R = x & mask;
+    #pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t F = (uint32_t)smix64(p.key ^ ((uint64_t)r << 40) ^ R) & mask;
+      const uint32_t t = R;
+      R = L ^ F;
+      L = t;
+    }
+    x = (L << p.h) | R;
+  } while (x >= p.n);
+  return x;
 }
 
 // LDS row strides (bf16 elements): site-major rows of 64 units, unit-major
@@ -222,8 +255,7 @@ constexpr int GRAD_WAVES = 1;
 __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const float* __restrict__ params,
                                                               const float* __restrict__ X,
                                                               const float* __restrict__ T, int64_t n,
-                                                              const int32_t* __restrict__ idx,
-                                                              float* __restrict__ partials) {
+                                                              MlpPerm perm, float* __restrict__ partials) {
   // the per-wave tiles and the final reduction buffer share the LDS
   constexpr size_t TILE_BYTES = sizeof(GradLds) * GRAD_WAVES;
   constexpr size_t RED_BYTES = sizeof(float) * GRAD_WAVES * (MLP_NPARAM + 1);
@@ -284,7 +316,7 @@ __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const float* __res
       if (g == 0) {
         float f[4] = {0.f, 0.f, 0.f, 0.f};
         if (live[h]) {
-          const int64_t src = idx ? (int64_t)idx[s] : s;
+          const int64_t src = perm.on ? (int64_t)feistel_perm((uint32_t)(perm.offset + s), perm) : s;
           #pragma unroll
           for (int k = 0; k < 4; ++k) { f[k] = X[src * 4 + k]; tgt[h][k] = T[src * 4 + k]; }
         }
@@ -465,30 +497,40 @@ __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const float* __res
 int mlp_grad_blocks(int64_t n) {
   const int64_t chunks = (n + 31) / 32;
   int64_t nb = (chunks + GRAD_WAVES - 1) / GRAD_WAVES;
-  return (int)(nb < 256 ? (nb > 0 ? nb : 1) : 256);
+  return (int)(nb < MLP_GRAD_MAX_BLOCKS ? (nb > 0 ? nb : 1) : MLP_GRAD_MAX_BLOCKS);
 }
 
-hipError_t launch_mlp_grad(const float* params, const float* X, const float* T, int64_t n, const int32_t* idx,
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* T, int64_t n, const MlpPerm& perm,
                            float* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_grad, dim3(mlp_grad_blocks(n)), dim3(64 * GRAD_WAVES), 0, s, params, X, T, n, idx,
+  hipLaunchKernelGGL(k_mlp_grad, dim3(mlp_grad_blocks(n)), dim3(64 * GRAD_WAVES), 0, s, params, X, T, n, perm,
                      partials);
   return hipGetLastError();
 }
 
-// fixed-order sum of the block partials: grad[p] and loss = sum / (4 n)
+// fixed-order sum of the block partials: grad[p] and loss = sum / (4 n).
+// A block owns 64 parameters; its 4 thread groups sum the partials of
+// blocks b = q (mod 4) in increasing b, then the 4 group sums are added in
+// group order.
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ partials, int nblocks, int64_t n,
                                                     float* __restrict__ grad, float* __restrict__ loss) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p > MLP_NPARAM) return;
+  __shared__ float red[4][64];
+  const int q = threadIdx.x >> 6, j = threadIdx.x & 63;
+  const int p = blockIdx.x * 64 + j;
   float s = 0.f;
-  for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * (MLP_NPARAM + 1) + p];
-  if (p < MLP_NPARAM) grad[p] = s;
-  else if (loss) *loss = s / (4.0f * (float)n);
+  if (p <= MLP_NPARAM)
+    for (int b = q; b < nblocks; b += 4) s += partials[(int64_t)b * (MLP_NPARAM + 1) + p];
+  red[q][j] = s;
+  __syncthreads();
+  if (q == 0 && p <= MLP_NPARAM) {
+    const float t = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    if (p < MLP_NPARAM) grad[p] = t;
+    else if (loss) *loss = t / (4.0f * (float)n);
+  }
 }
 
 hipError_t launch_mlp_reduce(const float* partials, int nblocks, int64_t n, float* grad, float* loss,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, partials, nblocks, n, grad,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 63) / 64), dim3(256), 0, s, partials, nblocks, n, grad,
                      loss);
   return hipGetLastError();
 }
