@@ -80,7 +80,8 @@ def cylinder_leg(args, torch, lbm, W, net):
     d, rho, u = W.CONFIGS["cylinder_2400x800_re20000_fstarM"]()
     e0 = W.iso_energy(u[0], u[1])
     out = {"lattice": "%dx%d" % (d["nx"], d["ny"]), "steps": args.cyl_steps}
-    for name, start in (("rest", lbm.LBM_START_DEFAULT), ("mlp", lbm.LBM_START_MLP)):
+    for name, start in (("rest", lbm.LBM_START_DEFAULT), ("mlp", lbm.LBM_START_MLP),
+                        ("previous_step", lbm.LBM_START_PREV)):
         cfg = lbm.config_from_workload(d, lbm.LBM_FP32, fstar_start=start,
                                        net=net if start == lbm.LBM_START_MLP else None)
         lat = lbm.Lattice(cfg, rho, u, e0)

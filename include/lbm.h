@@ -51,8 +51,10 @@ enum { LBM_FP32 = 0, LBM_FP64 = 1 };
 enum { LBM_BC_PERIODIC = 0, LBM_BC_ZEROGRAD = 1, LBM_BC_FREESLIP = 2, LBM_BC_INLET_EQ = 3 };
 /* collision: LBGK (eq. lbgkLB) or ELBM (eq. elbmLB) */
 enum { LBM_COLL_LBGK = 0, LBM_COLL_ELBM = 1 };
-/* f*_M Newton start */
-enum { LBM_START_DEFAULT = 0, LBM_START_CLOSED_FORM = 1, LBM_START_MLP = 2 };
+/* f*_M Newton start: isothermal rest state at the site density; the
+   mass-momentum closed form of Sec. 4.2; the warm-start network; the
+   multipliers already held (previous time step / contents of mu) */
+enum { LBM_START_DEFAULT = 0, LBM_START_CLOSED_FORM = 1, LBM_START_MLP = 2, LBM_START_PREV = 3 };
 
 typedef struct lbm_ctx lbm_ctx; /* opaque; owns all device memory it allocates */
 typedef struct lbm_mlp lbm_mlp; /* opaque; owns weights and optimiser state    */
@@ -209,7 +211,8 @@ int lbm_fstar_set_tolerance(lbm_fstar* s, double tol, double tol32, int32_t max3
  * Solves n sites.  M: device double [4][n] (rho, rho u1, rho u2, 2E);
  * mu: device double [4][n] output; start: LBM_START_DEFAULT (isothermal
  * rest state at the site density), LBM_START_CLOSED_FORM (mass-momentum
- * closed form of Sec. 4.2) or LBM_START_MLP (network net); iters, status:
+ * closed form of Sec. 4.2), LBM_START_MLP (network net) or LBM_START_PREV
+ * (the values in mu on entry); iters, status:
  * optional device uint8 [n] (Newton updates; 0 ok, 1 fallback ok,
  * 2 infeasible, 3 failed).  stats (host, optional) synchronises the stream
  * and returns LBM_E_NOCONV if any site failed; without stats the call is

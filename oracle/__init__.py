@@ -84,6 +84,9 @@ def lib():
         L.or_elbm_alpha.restype = C.c_double
         L.or_init.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _D]
         L.or_step.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _I64, C.POINTER(_Info)]
+        L.or_step_sites.argtypes = [C.POINTER(_Cfg), _D, _I64, C.c_int64, _I64, C.c_int64, _D]
+        L.or_site_dS.argtypes = [C.POINTER(_Cfg), _D, C.c_int64]
+        L.or_site_dS.restype = C.c_double
         L.or_mlp_forward.argtypes = [_D, _D, C.c_int64, _D, C.c_int]
         L.or_mlp_forward.restype = C.c_double
         L.or_mlp_loss_grad.argtypes = [_D, _D, _D, C.c_int64, _D, C.c_int]
@@ -222,6 +225,23 @@ def step(cfg: _Cfg, f_in: np.ndarray) -> dict:
     return dict(f=f_out, dS=dS, sel=sel[:info.n_selected].copy(), n_above=info.n_above,
                 n_selected=info.n_selected, n_invalid=info.n_invalid,
                 n_fallback=info.n_fallback, sums=np.array(info.sums[:]))
+
+
+def step_sites(cfg: _Cfg, f_in: np.ndarray, sites, selected) -> np.ndarray:
+    """f(t+1) at the given output sites [ns][Q], from f(t) with the given set
+    of sites returned to quasiequilibrium (for lattices too large for step)."""
+    f_in = np.ascontiguousarray(f_in, np.float64)
+    sites = np.ascontiguousarray(sites, np.int64)
+    sel = np.ascontiguousarray(np.asarray(selected, np.int64).reshape(-1))
+    out = np.zeros((sites.size, cfg.Q))
+    lib().or_step_sites(C.byref(cfg), _p(f_in), sites.ctypes.data_as(_I64), sites.size,
+                        sel.ctypes.data_as(_I64) if sel.size else None, sel.size, _p(out))
+    return out
+
+
+def site_dS(cfg: _Cfg, f_in: np.ndarray, sites) -> np.ndarray:
+    f_in = np.ascontiguousarray(f_in, np.float64)
+    return np.array([lib().or_site_dS(C.byref(cfg), _p(f_in), int(s)) for s in np.asarray(sites).reshape(-1)])
 
 
 def run(cfg: _Cfg, f: np.ndarray, nsteps: int) -> np.ndarray:

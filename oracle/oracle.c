@@ -645,6 +645,62 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS, int6
   return 0;
 }
 
+/*
+ * The same time step evaluated only at the output sites `sites` (out:
+ * [ns][Q]), with the set of sites returned to quasiequilibrium given by the
+ * caller (sel, nsel).  Each output population is the post-collision value of
+ * its free-flight source (or_source), computed from that source site alone.
+ */
+int or_step_sites(const or_cfg* c, const double* f_in, const int64_t* sites, int64_t ns, const int64_t* sel,
+                  int64_t nsel, double* out)
+{
+  int Q = c->Q;
+  int64_t nx = c->nx, N = c->nx * c->ny;
+  int32_t vx[9], vy[9];
+  double w[9];
+  or_velocities(Q, vx, vy, w);
+  double beta = 1.0 / (1.0 + 6.0 * c->nu);
+  double fin_in[9];
+  or_inlet_qe(c, fin_in);
+  for (int64_t k = 0; k < ns; ++k) {
+    int64_t x = sites[k] % nx, y = sites[k] / nx;
+    for (int i = 0; i < Q; ++i) {
+      double v = 0.0;
+      int64_t px, py;
+      int j;
+      if (or_solid(c, x, y)) v = 0.0;
+      else if (!or_source(c, vx, vy, x, y, i, &px, &py, &j)) v = fin_in[i];
+      else {
+        int64_t s = py * nx + px;
+        double f[9], fs[9], M[4];
+        for (int q = 0; q < Q; ++q) f[q] = f_in[(int64_t)q * N + s];
+        or_moments(Q, f, M);
+        or_site_qe(c, M, fs);
+        int chosen = 0;
+        for (int64_t r = 0; r < nsel; ++r)
+          if (sel[r] == s) chosen = 1;
+        double a = 2.0;
+        if (c->collision == OR_COLL_ELBM && !chosen) a = or_elbm_alpha(Q, f, fs);
+        v = chosen ? fs[j] : f[j] + a * beta * (fs[j] - f[j]);
+      }
+      out[k * Q + i] = v;
+    }
+  }
+  return 0;
+}
+
+/* Delta S of one site of a lattice (pre-collision populations f_in) */
+double or_site_dS(const or_cfg* c, const double* f_in, int64_t site)
+{
+  int Q = c->Q;
+  int64_t N = c->nx * c->ny;
+  double f[9], fs[9], M[4];
+  for (int q = 0; q < Q; ++q) f[q] = f_in[(int64_t)q * N + site];
+  or_moments(Q, f, M);
+  or_site_qe(c, M, fs);
+  return (double)or_delta_S(Q, f, fs);
+}
+
 /* ------------------------------------------------------------------------ */
 /* MLP 4 -> 64 -> 64 -> 4 with SiLU: the learned warm start                  */
 /* ------------------------------------------------------------------------ */

@@ -73,6 +73,10 @@ int or_init(const or_cfg* c, const double* rho0, const double* u0, const double*
 int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS,
             int64_t* sel, or_step_info* info);
 
+int or_step_sites(const or_cfg* c, const double* f_in, const int64_t* sites, int64_t ns, const int64_t* sel,
+                  int64_t nsel, double* out);
+double or_site_dS(const or_cfg* c, const double* f_in, int64_t site);
+
 /* MLP 4 -> 64 -> 64 -> 4 (SiLU), parameters flat (see oracle.c) */
 enum { OR_MLP_NPARAM = 4740 };
 double or_mlp_forward(const double* p, const double* x, int64_t n, double* y, int bf16);

@@ -130,7 +130,7 @@ int lbm_validate_config(const lbm_config* c) {
   if (c->qe == LBM_QE_ENTROPIC_M) {
     if (c->lattice != LBM_D2Q9) return fail(LBM_E_INVAL, "LBM_QE_ENTROPIC_M needs D2Q9");
     if (c->fstar_start != LBM_START_DEFAULT && c->fstar_start != LBM_START_CLOSED_FORM &&
-        c->fstar_start != LBM_START_MLP)
+        c->fstar_start != LBM_START_MLP && c->fstar_start != LBM_START_PREV)
       return fail(LBM_E_INVAL, "fstar_start must be one of LBM_START_*");
     if (c->fstar_start == LBM_START_MLP && !c->net) return fail(LBM_E_INVAL, "LBM_START_MLP needs cfg->net");
   }
@@ -348,6 +348,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
     f.max64 = 6;
     c->fkind = cfg->fstar_start == LBM_START_CLOSED_FORM ? START_CLOSED
                : cfg->fstar_start == LBM_START_MLP        ? START_WARM
+               : cfg->fstar_start == LBM_START_PREV       ? START_PREV
                                                           : START_REST;
     a.Mbuf = c->Mbuf;
     a.mu = c->mubuf;

@@ -88,8 +88,9 @@ int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_
                     uint8_t* iters, uint8_t* status, lbm_solve_stats* st) {
   if (!s || !M || !mu) return lbm_internal_fail(LBM_E_INVAL, "solver, M and mu are required");
   if (n < 0 || n > s->cap) return lbm_internal_fail(LBM_E_INVAL, "n must be in [0, max_n]");
-  if (start != LBM_START_DEFAULT && start != LBM_START_CLOSED_FORM && start != LBM_START_MLP)
-    return lbm_internal_fail(LBM_E_INVAL, "start must be LBM_START_DEFAULT, _CLOSED_FORM or _MLP");
+  if (start != LBM_START_DEFAULT && start != LBM_START_CLOSED_FORM && start != LBM_START_MLP &&
+      start != LBM_START_PREV)
+    return lbm_internal_fail(LBM_E_INVAL, "start must be one of LBM_START_*");
   if (start == LBM_START_MLP && !net) return lbm_internal_fail(LBM_E_INVAL, "LBM_START_MLP needs a network");
   FstarArgs a{};
   a.M = M;
@@ -107,6 +108,7 @@ int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_
   a.max64 = s->max64;
   int kind = START_REST;
   if (start == LBM_START_CLOSED_FORM) kind = START_CLOSED;
+  if (start == LBM_START_PREV) kind = START_PREV;
   if (start == LBM_START_MLP) {
     kind = START_WARM;
     if (n > 0) HIPCHK(launch_mlp_warm(net->params, net->norm, M, n, s->warm, s->stream));

@@ -117,6 +117,12 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
           s.X = __expf(a.warm[n + i]);
           s.Y = __expf(a.warm[2 * n + i]);
           s.Z = __expf(a.warm[3 * n + i]);
+        } else if (START == START_PREV) {
+          // the multipliers already in mu (e.g. the previous time step's)
+          s.a = __expf((float)a.mu[i]) / (float)rho;
+          s.X = __expf((float)a.mu[n + i]);
+          s.Y = __expf((float)a.mu[2 * n + i]);
+          s.Z = __expf((float)a.mu[3 * n + i]);
         } else {
           s.a = 4.0f / 9.0f;
           s.X = 1.0f;
@@ -243,6 +249,7 @@ hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s) {
   if (nb > 0) {
     if (start == START_CLOSED) hipLaunchKernelGGL((k_fstar<START_CLOSED>), dim3(nb), dim3(256), 0, s, a);
     else if (start == START_WARM) hipLaunchKernelGGL((k_fstar<START_WARM>), dim3(nb), dim3(256), 0, s, a);
+    else if (start == START_PREV) hipLaunchKernelGGL((k_fstar<START_PREV>), dim3(nb), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_fstar<START_REST>), dim3(nb), dim3(256), 0, s, a);
   }
   hipLaunchKernelGGL(k_fstar_fallback, dim3(64), dim3(64), 0, s, a);

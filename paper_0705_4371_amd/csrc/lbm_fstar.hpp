@@ -7,7 +7,7 @@
 
 namespace lbm {
 
-enum : int { START_REST = 0, START_CLOSED = 1, START_WARM = 2 };
+enum : int { START_REST = 0, START_CLOSED = 1, START_WARM = 2, START_PREV = 3 };
 
 struct FstarStats {
   unsigned long long hist[16];   // Newton updates per site (FP32 + FP64 phases)
@@ -18,7 +18,7 @@ struct FstarStats {
 struct FstarArgs {
   const double* M;      // [4][n]
   int64_t n;
-  double* mu;           // [4][n]
+  double* mu;           // [4][n] (START_PREV: read as the start, then overwritten)
   const float* warm;    // [4][n]: (mu0 - ln rho, mu1, mu2, mu3) start, START_WARM only
   uint8_t* iters;       // [n] or null
   uint8_t* status;      // [n] or null: 0 ok, 1 fallback ok, 2 infeasible, 3 failed

@@ -23,7 +23,7 @@ LBM_QE_POLY, LBM_QE_ENTROPIC_MM, LBM_QE_ENTROPIC_M = 0, 1, 2
 LBM_FP32, LBM_FP64 = 0, 1
 LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ = 0, 1, 2, 3
 LBM_COLL_LBGK, LBM_COLL_ELBM = 0, 1
-LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP = 0, 1, 2
+LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP, LBM_START_PREV = 0, 1, 2, 3
 
 
 class lbm_config(C.Structure):

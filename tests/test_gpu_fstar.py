@@ -127,3 +127,22 @@ def test_full_size_moment_field():
     mun = mu.cpu().numpy()
     _check_sites(M, mun, np.random.default_rng(1).integers(0, M.shape[1], 200))
     s.close()
+
+
+def test_previous_multipliers_start():
+    """LBM_START_PREV: solving again from the converged multipliers needs no
+    update; from slightly perturbed ones, one or two."""
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    M = W.moment_field(nx=128, ny=64, seed=7)
+    Mt = torch.from_numpy(M).cuda()
+    s = lbm.FstarSolver(M.shape[1])
+    mu, it, status, st = s.solve(Mt)
+    mu2, it2, _, st2 = s.solve(Mt, start=lbm.LBM_START_PREV, mu=mu.clone())
+    assert st2.n_failed == 0 and it2.max().item() <= 1
+    assert (mu2 - mu).abs().max().item() < 1e-9
+    M3 = M * (1 + 1e-3 * np.random.default_rng(2).uniform(-1, 1, M.shape))
+    mu3, it3, _, st3 = s.solve(torch.from_numpy(M3).cuda(), start=lbm.LBM_START_PREV, mu=mu.clone())
+    assert st3.n_failed == 0 and st3.max_resid <= 1e-10
+    assert it3.float().mean().item() < it.float().mean().item()
+    s.close()

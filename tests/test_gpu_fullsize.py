@@ -1,0 +1,142 @@
+"""Full-size GPU parity on sampled outputs: the lattices of the study at their
+real sizes, through the same kernels bench.py times.  The oracle evaluates
+one step at sampled output sites (oracle.step_sites) given the selected set,
+and Delta S at every GPU candidate and at sampled other sites.
+
+Bars as in test_gpu_step.py: FP32 populations within 1e-5 of the oracle
+(relative to max |f|), candidate Delta S within 1e-12 of max(Delta S, delta),
+no false negatives among sampled sites, the selected set equal to the top k
+of the candidates by (oracle Delta S desc, site asc) except at sites within
+1e-12 of the k-th value.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from _gpu_common import exempt_sites, lattice, say, torch_gpu
+
+pytestmark = pytest.mark.gpu
+FP32 = 0
+
+
+def _check_selection(oc, d, f, sites, ds, sel):
+    """Candidates and selection of one GPU step from populations f."""
+    delta, k = d["delta"], d["k"]
+    ods = oracle.site_dS(oc, f, sites)
+    fin = np.isfinite(ods)
+    assert np.array_equal(np.isfinite(ds), fin)
+    scale = np.maximum(ods[fin], delta)
+    err = np.abs(ds[fin] - ods[fin]) / scale
+    assert err.max(initial=0.0) <= 1e-12, err.max()
+    assert (ods > delta * (1 - 1e-12)).all()
+    order = sorted(zip((-ods).tolist(), sites.tolist()))
+    want = [s for _, s in order[:k]]
+    kth = -order[min(k, len(order)) - 1][0] if order else None
+    diff = np.array(sorted(set(want) ^ set(sel.tolist())), dtype=np.int64)
+    if diff.size:
+        od = dict(zip(sites.tolist(), ods.tolist()))
+        assert all(abs(od[s] - kth) <= 1e-12 * max(od[s], kth) for s in diff), diff[:10]
+    return set(sel.tolist())
+
+
+def _sampled_step(lat, d, f, rng, extra_sites=(), nsample=3000):
+    """One GPU step from f (the GPU's canonical state), checked at sampled sites."""
+    oc = oracle.cfg_from_dict(d)
+    lat.step(1)
+    st, sel, _ = lat.stats(sel_cap=d["k"])
+    sites, ds = lat.candidates()
+    assert st.n_above_delta == sites.size
+    _check_selection(oc, d, f, sites, ds, sel)
+    # no false negatives among sampled non-candidates
+    N = d["nx"] * d["ny"]
+    cand = np.zeros(N, bool)
+    cand[sites] = True
+    probe = rng.integers(0, N, 20000)
+    probe = probe[~cand[probe]]
+    solid = d.get("solid", (0, 0, 0, 0))
+    ods = oracle.site_dS(oc, f, probe)
+    px, py = probe % d["nx"], probe // d["nx"]
+    insolid = (px >= solid[0]) & (px < solid[0] + solid[2]) & (py >= solid[1]) & (py < solid[1] + solid[3])
+    assert (ods[~insolid] <= d["delta"] * (1 + 1e-12)).all()
+    # populations at sampled output sites
+    g = lat.get_populations()
+    out_sites = np.unique(np.concatenate([rng.integers(0, N, nsample), np.asarray(extra_sites, np.int64),
+                                          sel[:200]]))
+    want = oracle.step_sites(oc, f, out_sites, sel)
+    got = g.reshape(d["Q"], -1)[:, out_sites].double().cpu().numpy().T
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say("  sampled %d sites, candidates %d, selected %d, rel err %.3g" % (out_sites.size, sites.size, sel.size, err))
+    assert err <= 1e-5
+    return g.double().cpu().numpy(), st
+
+
+def test_shear_layer_full_size():
+    torch = torch_gpu()
+    say("full-size shear layer 8192 x 4096 FP32")
+    d, rho, u = W.shear_layer()
+    lat = lattice(d, FP32, rho, u)
+    del rho, u
+    f = lat.get_populations()
+    # a band of perturbed rows: tens of thousands of sites above delta, n >> k
+    r = np.random.default_rng(0)
+    band = torch.from_numpy(1 + 0.05 * r.uniform(-1, 1, (9, 12, d["nx"]))).float().cuda()
+    f[:, 2000:2012, :] *= band
+    lat.set_populations(f)
+    f = lat.get_populations().double().cpu().numpy()
+    nx = d["nx"]
+    extra = np.concatenate([2000 * nx + np.arange(0, nx, 37), 2011 * nx + np.arange(5, nx, 41),
+                            np.arange(0, nx, 97), (d["ny"] - 1) * nx + np.arange(3, nx, 89)])
+    g, st = _sampled_step(lat, d, f, r, extra)
+    assert st.n_above_delta > 4 * d["k"] and st.n_selected == d["k"]
+    g, st = _sampled_step(lat, d, g, r, extra)    # the pull path
+    lat.close()
+
+
+def test_cylinder_full_size():
+    torch = torch_gpu()
+    say("full-size cylinder 1200 x 400 FP32")
+    d, rho, u = W.cylinder(re=20000.0)
+    lat = lattice(d, FP32, rho, u)
+    f = lat.get_populations()
+    r = np.random.default_rng(1)
+    x0, y0, w, h = d["solid"]
+    pert = torch.from_numpy(1 + 0.03 * r.uniform(-1, 1, (9, h + 40, w + 80))).float().cuda()
+    f[:, y0 - 20:y0 + h + 20, x0 - 20:x0 + w + 60] *= pert
+    f[:, y0:y0 + h, x0:x0 + w] = 0
+    lat.set_populations(f)
+    f = lat.get_populations().double().cpu().numpy()
+    nx, ny = d["nx"], d["ny"]
+    edges = np.concatenate([np.arange(0, ny) * nx, np.arange(0, ny) * nx + nx - 1, np.arange(nx),
+                            (ny - 1) * nx + np.arange(nx)])
+    ring = [(y * nx + x) for y in range(y0 - 2, y0 + h + 2) for x in range(x0 - 2, x0 + w + 2)]
+    extra = np.concatenate([edges, np.array(ring)])
+    g, st = _sampled_step(lat, d, f, r, extra)
+    assert st.n_selected == min(d["k"], st.n_above_delta) and st.n_above_delta > 0
+    g, st = _sampled_step(lat, d, g, r, extra)
+    lat.close()
+
+
+def test_cylinder_fstarM_full_size():
+    torch = torch_gpu()
+    say("full-size f*_M cylinder 2400 x 800 FP32")
+    d, rho, u = W.CONFIGS["cylinder_2400x800_re20000_fstarM"]()
+    e0 = W.iso_energy(u[0], u[1])
+    lat = lattice(d, FP32, rho, u, twoE0=e0)
+    f = lat.get_populations()
+    r = np.random.default_rng(2)
+    x0, y0, w, h = d["solid"]
+    pert = torch.from_numpy(1 + 0.03 * r.uniform(-1, 1, (9, h + 40, w + 80))).float().cuda()
+    f[:, y0 - 20:y0 + h + 20, x0 - 20:x0 + w + 60] *= pert
+    f[:, y0:y0 + h, x0:x0 + w] = 0
+    lat.set_populations(f)
+    f = lat.get_populations().double().cpu().numpy()
+    nx, ny = d["nx"], d["ny"]
+    ring = [(y * nx + x) for y in range(y0 - 2, y0 + h + 2, 3) for x in range(x0 - 2, x0 + w + 2, 3)]
+    extra = np.concatenate([np.arange(0, ny, 7) * nx, np.arange(0, ny, 7) * nx + nx - 1, np.array(ring)])
+    g, st = _sampled_step(lat, d, f, r, extra, nsample=1500)
+    assert st.n_selected == min(d["k"], st.n_above_delta) and st.n_above_delta > 0
+    assert st.n_fallback == 0
+    lat.close()

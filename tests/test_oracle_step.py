@@ -241,3 +241,20 @@ def test_shock_tube_ehrenfest_subdues_oscillations():
     tv_e = _total_variation(res["es"][0], 250, 700)
     assert res["es"][1] > 0
     assert tv_e < tv_l
+
+
+@pytest.mark.parametrize("qe", [oracle.QE_POLY, oracle.QE_ENTROPIC_M])
+def test_step_at_sites_equals_whole_step(qe):
+    """The per-site evaluation used on large lattices reproduces the whole
+    step (same selection) at every site, boundaries and solid included."""
+    cfg = oracle.make_cfg(Q=9, qe=qe, nx=23, ny=11, nu=1e-3, delta=1e-5, k=6,
+                          bc=(W.INLET_EQ, W.ZEROGRAD, W.FREESLIP, W.FREESLIP),
+                          inlet_rho=1.0, inlet_u=(0.05, 0.0), solid=(8, 4, 3, 3))
+    f = _near_eq_state(cfg, 14, amp=0.02)
+    f[:, 4:7, 8:11] = 0.0
+    out = oracle.step(cfg, f)
+    sites = np.arange(cfg.nx * cfg.ny)
+    g = oracle.step_sites(cfg, f, sites, out["sel"])
+    assert np.array_equal(g.T.reshape(out["f"].shape), out["f"])
+    ds = oracle.site_dS(cfg, f, sites[:40])
+    assert np.array_equal(ds, out["dS"].reshape(-1)[:40])
