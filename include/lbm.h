@@ -49,7 +49,10 @@ enum { LBM_FP32 = 0, LBM_FP64 = 1 };
 /* boundary rules; west/east accept PERIODIC, ZEROGRAD, INLET_EQ;
    south/north accept PERIODIC, ZEROGRAD, FREESLIP */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_ZEROGRAD = 1, LBM_BC_FREESLIP = 2, LBM_BC_INLET_EQ = 3 };
-/* collision: LBGK (eq. lbgkLB) or ELBM (eq. elbmLB) */
+/* collision: LBGK (eq. lbgkLB), f' = f + 2 beta (f* - f); or ELBM
+   (eq. elbmLB), f' = f + alpha beta (f* - f) with alpha the nontrivial root
+   of S(f + alpha (f* - f)) = S(f) by bisection to 1e-15 (entropic
+   quasiequilibria only) */
 enum { LBM_COLL_LBGK = 0, LBM_COLL_ELBM = 1 };
 /* f*_M Newton start: isothermal rest state at the site density; the
    mass-momentum closed form of Sec. 4.2; the warm-start network; the

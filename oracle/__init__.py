@@ -82,6 +82,8 @@ def lib():
         L.or_delta_S.restype = C.c_longdouble
         L.or_elbm_alpha.argtypes = [C.c_int, _D, _D]
         L.or_elbm_alpha.restype = C.c_double
+        L.or_elbm_H.argtypes = [C.c_int, _D, _D, C.c_longdouble]
+        L.or_elbm_H.restype = C.c_longdouble
         L.or_init.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _D]
         L.or_step.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _I64, C.POINTER(_Info)]
         L.or_step_sites.argtypes = [C.POINTER(_Cfg), _D, _I64, C.c_int64, _I64, C.c_int64, _D]
@@ -173,6 +175,13 @@ def elbm_alpha(f, fs) -> float:
     f = np.ascontiguousarray(f, np.float64)
     fs = np.ascontiguousarray(fs, np.float64)
     return float(lib().or_elbm_alpha(len(f), _p(f), _p(fs)))
+
+
+def elbm_H(f, fs, a) -> float:
+    """S(f + a (f* - f)) - S(f) in the cancellation-free form (entropic f*)."""
+    f = np.ascontiguousarray(f, np.float64)
+    fs = np.ascontiguousarray(fs, np.float64)
+    return float(lib().or_elbm_H(len(f), _p(f), _p(fs), a))
 
 
 def make_cfg(Q=9, qe=QE_POLY, nx=16, ny=1, nu=1e-3, delta=float("inf"), k=0,

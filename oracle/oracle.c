@@ -364,34 +364,63 @@ static long double or_entropy(int Q, const long double* f)
 /*
  * ELBM (Sec. 3.2 and Sec. 4.1): alpha is the nontrivial root of
  * S(f + alpha (f* - f)) = S(f), found by bisection to an accuracy of 1e-15.
- * The entropy along the line is concave with its maximum at alpha = 1, so
- * the root lies in (1, alpha_max], alpha_max being the largest alpha that
- * keeps every population non-negative.  If no root lies there, alpha_max is
- * returned.  At f == f* (no direction) alpha = 2.
+ *
+ * Evaluation without cancellation.  With x_i = f*_i / f_i - 1 (f, f* > 0)
+ * and S(g) = -sum g ln(g/W):
+ *   S(f + a (f* - f)) - S(f)
+ *     = -a sum f x ln(f/W) - sum f (1 + a x) ln(1 + a x).
+ * For an entropic f* with the conserved moments of f, ln(f* / W) lies in the
+ * span of the moment rows, so sum (f* - f) ln(f* / W) = 0 and
+ * sum f x ln(f/W) = -sum f x ln(1 + x); with sum (f* - f) = 0 (mass row)
+ *   H(a) = sum_i f_i [a psi(x_i) - phi(a x_i)],
+ *   psi(x) = x ln(1 + x),  phi(y) = (1 + y) ln(1 + y) - y,
+ * in which every term is O(x^2); phi uses its Taylor series
+ * sum_{k>=2} (-1)^k y^k / (k (k-1)) for |y| < 0.1.  H(1) is Delta S, H is
+ * concave with its maximum at a = 1, and the root lies in (1, a_max], a_max
+ * the largest a that keeps every population non-negative (capped at 1000);
+ * if H(a_max) >= 0 there is no root below it and a_max is returned.
+ * A site with some f_i <= 0 or f*_i <= 0 has no entropy to conserve; it, and
+ * a site at f = f*, takes the LBGK mirror a = 2.
  */
+static long double or_phi_elbm(long double y)
+{
+  if (fabsl(y) < 0.1L) {
+    long double s = 0.0L, p = y * y;
+    for (int k = 2; k <= 22; ++k) {
+      s += ((k & 1) ? -p : p) / (long double)(k * (k - 1));
+      p *= y;
+    }
+    return s;
+  }
+  return (1.0L + y) * log1pl(y) - y;
+}
+
+long double or_elbm_H(int Q, const double* f, const double* fs, long double a)
+{
+  long double h = 0.0L;
+  for (int i = 0; i < Q; ++i) {
+    long double x = (long double)fs[i] / (long double)f[i] - 1.0L;
+    h += (long double)f[i] * (a * x * log1pl(x) - or_phi_elbm(a * x));
+  }
+  return h;
+}
+
 double or_elbm_alpha(int Q, const double* f, const double* fs)
 {
-  long double F[9], D[9];
+  long double amax = 1000.0L;
   int moving = 0;
-  long double amax = 1e30L;
   for (int i = 0; i < Q; ++i) {
-    F[i] = f[i];
-    D[i] = (long double)fs[i] - f[i];
-    if (D[i] != 0.0L) moving = 1;
-    if (D[i] < 0.0L) {
-      long double lim = -F[i] / D[i];
-      if (lim < amax) amax = lim;
-    }
+    if (!(f[i] > 0.0) || !(fs[i] > 0.0)) return 2.0;
+    long double x = (long double)fs[i] / (long double)f[i] - 1.0L;
+    if (x != 0.0L) moving = 1;
+    if (x < 0.0L && -1.0L / x < amax) amax = -1.0L / x;
   }
   if (!moving) return 2.0;
-  long double S0 = or_entropy(Q, F);
-  long double hi = amax < 1e3L ? amax : 1e3L, lo = 1.0L, tmp[9];
-  for (int i = 0; i < Q; ++i) tmp[i] = F[i] + hi * D[i];
-  if (or_entropy(Q, tmp) >= S0) return (double)hi;
+  long double lo = 1.0L, hi = amax;
+  if (or_elbm_H(Q, f, fs, hi) >= 0.0L) return (double)hi;
   while (hi - lo > 1e-15L) {
     long double mid = 0.5L * (lo + hi);
-    for (int i = 0; i < Q; ++i) tmp[i] = F[i] + mid * D[i];
-    if (or_entropy(Q, tmp) > S0) lo = mid;
+    if (or_elbm_H(Q, f, fs, mid) > 0.0L) lo = mid;
     else hi = mid;
   }
   return (double)(0.5L * (lo + hi));

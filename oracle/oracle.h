@@ -65,8 +65,9 @@ void or_fstar_from_mu(const double* mu, double* fs);
 /* nonequilibrium entropy (generalised Kullback form), long double */
 long double or_delta_S(int Q, const double* f, const double* fs);
 
-/* ELBM entropic involution parameter */
+/* ELBM entropic involution parameter and its entropy function */
 double or_elbm_alpha(int Q, const double* f, const double* fs);
+long double or_elbm_H(int Q, const double* f, const double* fs, long double a);
 
 /* whole lattice */
 int or_init(const or_cfg* c, const double* rho0, const double* u0, const double* twoE0, double* f);

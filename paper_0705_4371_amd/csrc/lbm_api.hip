@@ -136,8 +136,10 @@ int lbm_validate_config(const lbm_config* c) {
   }
   if (c->precision != LBM_FP32 && c->precision != LBM_FP64)
     return fail(LBM_E_INVAL, "precision must be LBM_FP32 or LBM_FP64, got %d", c->precision);
-  if (c->collision != LBM_COLL_LBGK)
-    return fail(LBM_E_INVAL, "only LBM_COLL_LBGK is available in this library build");
+  if (c->collision != LBM_COLL_LBGK && c->collision != LBM_COLL_ELBM)
+    return fail(LBM_E_INVAL, "collision must be LBM_COLL_LBGK or LBM_COLL_ELBM, got %d", c->collision);
+  if (c->collision == LBM_COLL_ELBM && c->qe == LBM_QE_POLY)
+    return fail(LBM_E_INVAL, "ELBM needs an entropic quasiequilibrium (LBM_QE_ENTROPIC_MM or _M)");
   if (c->nx < 2 || c->ny < 1) return fail(LBM_E_INVAL, "need nx >= 2 and ny >= 1 (got %lld x %lld)",
                                          (long long)c->nx, (long long)c->ny);
   if (c->lattice == LBM_D1Q3 && c->ny != 1) return fail(LBM_E_INVAL, "D1Q3 requires ny == 1");
@@ -301,6 +303,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   a.ntx = (cfg->nx + STEP_TX - 1) / STEP_TX;
   a.nblocks = a.ntx * cfg->ny;
   a.prec = cfg->precision;
+  a.coll = cfg->collision;
   a.Q = Q;
   a.qe = cfg->qe;
 

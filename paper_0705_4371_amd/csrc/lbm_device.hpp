@@ -233,6 +233,56 @@ __device__ __forceinline__ float dS_bound_poly(const float* f, const float* fs, 
   return ok ? u : __builtin_inff();
 }
 
+// ELBM (eq. (elbmLB)): alpha is the nontrivial root of
+// S(f + alpha (f* - f)) = S(f), by bisection to 1e-15.  For an entropic f*
+// with the conserved moments of f the entropy difference equals, exactly,
+//   H(a) = sum_i f_i [a x_i ln(1 + x_i) - phi(a x_i)],  x_i = f*_i / f_i - 1,
+//   phi(y) = (1 + y) ln(1 + y) - y,
+// a form free of cancellation (every term is O(x^2)); phi by its Taylor
+// series sum_{k>=2} (-1)^k y^k / (k (k-1)) for |y| < 0.1.  The root lies in
+// (1, a_max], a_max keeping every population >= 0 (capped at 1000); a site
+// with some f_i <= 0 or f*_i <= 0, or with f = f*, takes a = 2.
+__device__ __forceinline__ double elbm_phi(double y) {
+  if (__builtin_fabs(y) < 0.1) {
+    // Horner on y^2 sum_{k=2}^{19} c_k y^(k-2), c_k = (-1)^k / (k (k-1))
+    double s = -1.0 / (19.0 * 18.0);
+    #pragma unroll
+    for (int k = 18; k >= 2; --k) s = s * y + ((k & 1) ? -1.0 : 1.0) / (double)(k * (k - 1));
+    return s * y * y;
+  }
+  return (1.0 + y) * ::log1p(y) - y;
+}
+
+template <int Q>
+__device__ __forceinline__ double elbm_alpha(const double* f, const double* fs) {
+  double x[Q], px[Q];
+  double amax = 1000.0;
+  bool moving = false;
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (!(f[i] > 0.0) || !(fs[i] > 0.0)) return 2.0;
+    x[i] = fs[i] / f[i] - 1.0;
+    px[i] = f[i] * x[i] * ::log1p(x[i]);  // f psi(x)
+    moving |= x[i] != 0.0;
+    if (x[i] < 0.0) amax = fmin(amax, -1.0 / x[i]);
+  }
+  if (!moving) return 2.0;
+  auto H = [&](double a) {
+    double h = 0.0;
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) h += a * px[i] - f[i] * elbm_phi(a * x[i]);
+    return h;
+  };
+  double lo = 1.0, hi = amax;
+  if (H(hi) >= 0.0) return hi;
+  for (int it = 0; it < 80 && hi - lo > 1e-15; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (H(mid) > 0.0) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 // FP64 Delta S (Sec. 3.3 Kullback form, generalised by -f + f* so that it
 // stays >= 0 when masses differ by round-off); +inf for f < 0 or f* <= 0.
 template <int Q>

@@ -89,7 +89,7 @@ __device__ __forceinline__ void fstar_from_mu_buf(const double* __restrict__ mu,
 // ---------------------------------------------------------------------------
 // k_step
 // ---------------------------------------------------------------------------
-template <typename T, int Q, int QE, bool PULL>
+template <typename T, int Q, int QE, bool PULL, bool ELBM = false>
 __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   const T* __restrict__ A = (const T*)a.A;
   T* __restrict__ B = (T*)a.B;
@@ -160,9 +160,16 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
     scr = !(ds < thr);
   }
 
-  // LBGK collision f' = f + 2 beta (f* - f), written at the origin site
+  // LBGK collision f' = f + 2 beta (f* - f) (eq. (lbgkLB)), or ELBM
+  // f' = f + alpha beta (f* - f) (eq. (elbmLB)); written at the origin site
   if (fluid) {
-    const T b2 = T(g.beta2);
+    T b2 = T(g.beta2);
+    if constexpr (ELBM) {
+      double fd[Q], fsd[Q];
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) { fd[i] = (double)f[i]; fsd[i] = (double)fs[i]; }
+      b2 = T(0.5 * g.beta2 * elbm_alpha<Q>(fd, fsd));
+    }
     const int64_t o = y * g.pitch + x;
     #pragma unroll
     for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = f[i] + b2 * (fs[i] - f[i]);
@@ -628,7 +635,10 @@ __global__ __launch_bounds__(256) void k_init_M_pops(StepArgs a) {
 template <typename T, int Q, int QE, bool PULL>
 static hipError_t step_t(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) { hipError_t e = hipEventRecord(ev0, s); if (e != hipSuccess) return e; }
-  hipLaunchKernelGGL((k_step<T, Q, QE, PULL>), dim3((unsigned)a.nblocks), dim3(STEP_TX), 0, s, a);
+  if (QE != QE_POLY && a.coll == 1)
+    hipLaunchKernelGGL((k_step<T, Q, QE, PULL, QE != QE_POLY>), dim3((unsigned)a.nblocks), dim3(STEP_TX), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_step<T, Q, QE, PULL>), dim3((unsigned)a.nblocks), dim3(STEP_TX), 0, s, a);
   if (ev1) { hipError_t e = hipEventRecord(ev1, s); if (e != hipSuccess) return e; }
   if (a.g.ds_on) {
     hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(512), dim3(256), 0, s, a);

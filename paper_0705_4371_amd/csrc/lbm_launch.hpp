@@ -55,6 +55,7 @@ struct StepArgs {
   float thr_a, thr_b;  // FP32 screen threshold: thr_a - thr_b * sqrt(rho)
   int64_t ntx, nblocks;
   int prec, Q, qe;
+  int coll;  // 0 LBGK, 1 ELBM
 };
 
 // launch one step's kernels (fused step, rank, select, reset) on stream s;

@@ -153,7 +153,8 @@ def config_from_workload(d: dict, precision: int, stream=None, fstar_start=LBM_S
                     nx=d["nx"], ny=d["ny"], nu=d["nu"], delta=d.get("delta", math.inf),
                     k=d.get("k", 0), bc=d.get("bc", (LBM_BC_PERIODIC,) * 4),
                     inlet_rho=d.get("inlet_rho", 1.0), inlet_u=d.get("inlet_u", (0.0, 0.0)),
-                    solid=d.get("solid", (0, 0, 0, 0)), fstar_start=fstar_start, stream=stream)
+                    solid=d.get("solid", (0, 0, 0, 0)), fstar_start=fstar_start,
+                    collision=d.get("collision", LBM_COLL_LBGK), stream=stream)
     if net is not None:
         c.net = net.h
     return c

@@ -103,8 +103,8 @@ def test_cylinder_full_size():
     f = lat.get_populations()
     r = np.random.default_rng(1)
     x0, y0, w, h = d["solid"]
-    pert = torch.from_numpy(1 + 0.03 * r.uniform(-1, 1, (9, h + 40, w + 80))).float().cuda()
-    f[:, y0 - 20:y0 + h + 20, x0 - 20:x0 + w + 60] *= pert
+    pert = torch.from_numpy(1 + 0.1 * r.uniform(-1, 1, (9, h + 40, w + 80))).float().cuda()
+    f[:, y0 - 20:y0 + h + 20, x0 - 20:x0 + w + 60] *= pert    # Delta S ~ 2e-3 > delta = 1e-3 at many sites
     f[:, y0:y0 + h, x0:x0 + w] = 0
     lat.set_populations(f)
     f = lat.get_populations().double().cpu().numpy()
@@ -128,8 +128,8 @@ def test_cylinder_fstarM_full_size():
     f = lat.get_populations()
     r = np.random.default_rng(2)
     x0, y0, w, h = d["solid"]
-    pert = torch.from_numpy(1 + 0.03 * r.uniform(-1, 1, (9, h + 40, w + 80))).float().cuda()
-    f[:, y0 - 20:y0 + h + 20, x0 - 20:x0 + w + 60] *= pert
+    pert = torch.from_numpy(1 + 0.1 * r.uniform(-1, 1, (9, h + 40, w + 80))).float().cuda()
+    f[:, y0 - 20:y0 + h + 20, x0 - 20:x0 + w + 60] *= pert    # Delta S ~ 2e-3 > delta = 1e-3 at many sites
     f[:, y0:y0 + h, x0:x0 + w] = 0
     lat.set_populations(f)
     f = lat.get_populations().double().cpu().numpy()

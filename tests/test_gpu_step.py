@@ -241,3 +241,31 @@ def test_entropic_fstarM_network_start_with_fallback():
     assert st.n_fallback > 0
     lat.close()
     net.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_elbm_shock_tube(prec):
+    """ELBM (eq. elbmLB) with Ehrenfests' steps on the shock tube (the
+    configuration of Fig. 1 (i): entropic QE, nu = 1e-9, (k, delta) = (4, 1e-4))."""
+    d, rho, u = W.shock_tube(delta=1e-4)
+    d = dict(d, qe=W.QE_ENTROPIC_MM, collision=1)
+    _run(d, rho, u[:1], prec, 17, 0.05, nsteps=4, label="elbm shock")
+
+
+def test_elbm_shock_tube_400_steps_fp64():
+    torch = torch_gpu()
+    d, rho, u = W.shock_tube(delta=1e-4)
+    d = dict(d, qe=W.QE_ENTROPIC_MM, collision=1)
+    lat = lattice(d, FP64, rho, u[:1])
+    f = lat.get_populations().double().cpu().numpy()
+    for s in range(400):
+        g, o, st = compare_step(lat, d, f, 1e-12, label="elbm400 step %d" % s)
+        f = g
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_elbm_d2q9(prec):
+    d, rho, u = W.shear_layer(nx=140, ny=30, k=9, delta=1e-5, width=8.0)
+    d = dict(d, qe=W.QE_ENTROPIC_MM, collision=1)
+    _run(d, rho, u, prec, 18, 0.03, label="elbm d2q9")

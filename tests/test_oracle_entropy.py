@@ -97,22 +97,47 @@ def test_invalid_sites():
     assert abs(oracle.delta_S(f, fs) - want) < 1e-15
 
 
+def _mm_perturbed(r, scale, Q=9):
+    """An entropic mass-momentum quasiequilibrium and a state with its mass
+    and momentum (so that f* is the quasiequilibrium of f)."""
+    vx, vy, w = oracle.velocities(Q)
+    u2 = r.uniform(-0.1, 0.1) if Q == 9 else 0.0
+    fs = oracle.qe_entropic_mm(Q, r.uniform(0.5, 1.5), r.uniform(-0.1, 0.1), u2)
+    d = scale * fs * r.uniform(-1, 1, Q)
+    A = np.stack([np.ones(Q), vx, vy]).astype(float)[: 2 if Q == 3 else 3]
+    d -= A.T @ np.linalg.solve(A @ A.T, A @ d)
+    return fs + d, fs, w
+
+
+def test_elbm_entropy_function_equals_entropy_difference():
+    """The cancellation-free H(a) equals S(f + a(f* - f)) - S(f) (50-digit
+    decimal) where that difference is well conditioned."""
+    decimal.getcontext().prec = 60
+    D = decimal.Decimal
+    r = np.random.default_rng(8)
+    for Q in (3, 9):
+        for _ in range(20):
+            f, fs, w = _mm_perturbed(r, 0.1, Q)
+            for a in (0.5, 1.0, 1.7, 2.0, 2.3):
+                if not (f + a * (fs - f) > 0).all():
+                    continue
+                Df, Dfs, Dw, Da = [D(float(v)) for v in f], [D(float(v)) for v in fs], [D(float(v)) for v in w], D(a)
+                g = [x + Da * (y - x) for x, y in zip(Df, Dfs)]
+                S = lambda h: -sum(hi * (hi / wi).ln() for hi, wi in zip(h, Dw))
+                want = float(S(g) - S(Df))
+                # the exact rewrite drops sum (f* - f)(1 + ln(f*/W)), which is
+                # zero up to the FP64 rounding of f*
+                corr = float(sum((y - x) * (D(1) + (y / wi).ln()) for x, y, wi in zip(Df, Dfs, Dw)))
+                assert abs(oracle.elbm_H(f, fs, a) - (want + a * corr)) <= 1e-14 * max(abs(want), 1e-6)
+
+
 def test_elbm_alpha_constant_entropy_and_lbgk_limit():
-    """S(f + alpha (f* - f)) = S(f) at the returned alpha; alpha -> 2 (the
-    LBGK mirror) as f -> f*."""
-    _, _, w = oracle.velocities(9)
+    """H(alpha) = 0 at the returned alpha (the root is bracketed to 1e-15);
+    alpha -> 2 (the LBGK mirror) as f -> f*."""
     r = np.random.default_rng(6)
-    for scale in (1e-1, 1e-2, 1e-3):
+    for scale in (1e-1, 1e-2, 1e-3, 1e-5, 1e-7):
         for _ in range(10):
-            fs = oracle.qe_entropic_mm(9, r.uniform(0.5, 1.5), r.uniform(-0.1, 0.1), r.uniform(-0.1, 0.1))
-            d = scale * fs * r.uniform(-1, 1, 9)
-            # keep mass and momentum (the entropic QE of f is then fs)
-            vx, vy, _ = oracle.velocities(9)
-            A = np.stack([np.ones(9), vx, vy]).astype(float)
-            d -= A.T @ np.linalg.solve(A @ A.T, A @ d)
-            f = fs + d
+            f, fs, w = _mm_perturbed(r, scale)
             a = oracle.elbm_alpha(f, fs)
-            S0 = _perfect_entropy(f, w)
-            S1 = _perfect_entropy(f + a * (fs - f), w)
-            assert abs(S1 - S0) < 1e-12
+            assert oracle.elbm_H(f, fs, a - 1e-14) > 0 > oracle.elbm_H(f, fs, a + 1e-14)
             assert abs(a - 2.0) < 5 * scale

@@ -258,3 +258,29 @@ def test_step_at_sites_equals_whole_step(qe):
     assert np.array_equal(g.T.reshape(out["f"].shape), out["f"])
     ds = oracle.site_dS(cfg, f, sites[:40])
     assert np.array_equal(ds, out["dS"].reshape(-1)[:40])
+
+
+def test_elbm_step_conserves_entropy_at_beta_one():
+    """ELBM with beta = 1 (nu = 0) replaces every f by its entropic
+    involution, which keeps the entropy (Sec. 3.2); free flight keeps it too,
+    so the total perfect entropy is unchanged, while LBGK changes it."""
+    for Q, ny in ((3, 1), (9, 7)):
+        cfg_e = oracle.make_cfg(Q=Q, qe=oracle.QE_ENTROPIC_MM, nx=15, ny=ny, nu=0.0,
+                                collision=oracle.COLL_ELBM)
+        cfg_l = oracle.make_cfg(Q=Q, qe=oracle.QE_ENTROPIC_MM, nx=15, ny=ny, nu=0.0)
+        f = _near_eq_state(cfg_e, 15, amp=0.05)
+        _, _, w = oracle.velocities(Q)
+        S = lambda h: -np.sum(h * np.log(h / w[:, None, None]))
+        se = S(oracle.step(cfg_e, f)["f"])
+        sl = S(oracle.step(cfg_l, f)["f"])
+        assert abs(se - S(f)) < 1e-12 * abs(S(f))
+        assert abs(sl - S(f)) > 1e3 * abs(se - S(f))
+
+
+def test_elbm_reduces_to_lbgk_near_equilibrium():
+    cfg_e = oracle.make_cfg(Q=9, qe=oracle.QE_ENTROPIC_MM, nx=9, ny=5, nu=1e-3, collision=oracle.COLL_ELBM)
+    cfg_l = oracle.make_cfg(Q=9, qe=oracle.QE_ENTROPIC_MM, nx=9, ny=5, nu=1e-3)
+    for amp in (1e-2, 1e-3, 1e-4):
+        f = _near_eq_state(cfg_e, 16, amp=amp)
+        d = np.abs(oracle.step(cfg_e, f)["f"] - oracle.step(cfg_l, f)["f"]).max()
+        assert d < 2 * amp * amp
