@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 QE_POLY, QE_ENTROPIC_MM, QE_ENTROPIC_M = 0, 1, 2
-BC_PERIODIC, BC_ZEROGRAD, BC_FREESLIP, BC_INLET_EQ = 0, 1, 2, 3
+BC_PERIODIC, BC_ZEROGRAD, BC_FREESLIP, BC_INLET_EQ, BC_OUTLET_EQ = 0, 1, 2, 3, 4
 COLL_LBGK, COLL_ELBM = 0, 1
 MLP_NPARAM = 4740
 
@@ -78,6 +78,8 @@ def lib():
         L.or_fstar_newton.argtypes = [_D, C.c_double, C.c_int, _D, _D]
         L.or_fstar_scalar.argtypes = [_D, _D]
         L.or_fstar_from_mu.argtypes = [_D, _D]
+        L.or_dft_power.argtypes = [_D, C.c_int64, _D]
+        L.or_dft_power.restype = None
         L.or_delta_S.argtypes = [C.c_int, _D, _D]
         L.or_delta_S.restype = C.c_longdouble
         L.or_elbm_alpha.argtypes = [C.c_int, _D, _D]
@@ -251,6 +253,16 @@ def step_sites(cfg: _Cfg, f_in: np.ndarray, sites, selected) -> np.ndarray:
 def site_dS(cfg: _Cfg, f_in: np.ndarray, sites) -> np.ndarray:
     f_in = np.ascontiguousarray(f_in, np.float64)
     return np.array([lib().or_site_dS(C.byref(cfg), _p(f_in), int(s)) for s in np.asarray(sites).reshape(-1)])
+
+
+def dft_power(x) -> np.ndarray:
+    """|DFT|^2 of a real signal at bins 0..n/2, by the definition (or_dft_power);
+    the shedding frequency of Sec. 4.2 is the dominant bin of the last quarter
+    of the recorded velocity."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1)
+    out = np.zeros(x.size // 2 + 1)
+    lib().or_dft_power(_p(x), x.size, _p(out))
+    return out
 
 
 def run(cfg: _Cfg, f: np.ndarray, nsteps: int) -> np.ndarray:

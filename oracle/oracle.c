@@ -472,10 +472,13 @@ static void or_inlet_qe(const or_cfg* c, double* fs)
  * Where f_i(x, y, t+1) comes from (free flight, Sec. 3, with the boundary
  * rules of Sec. 4.2 as read for these configurations):
  *   returns 1: the post-collision population *pj at (*px, *py);
- *   returns 0: the inlet quasiequilibrium value of population i.
+ *   returns 0: the inlet quasiequilibrium value of population i;
+ *   returns 2: the outlet rule: population i of the quasiequilibrium at the
+ *     density and velocity of f(*px, y, t+1), *px the penultimate column.
  * Rules, in this order:
  *   x outside: periodic wrap | zero-gradient: the value that the adjacent
- *     inner column receives | inlet: quasiequilibrium at the inlet state;
+ *     inner column receives | inlet: quasiequilibrium at the inlet state |
+ *     outlet: quasiequilibrium of the penultimate column (Sec. 4.2);
  *   y outside: periodic wrap | free-slip: specular reflection, i.e. the
  *     population with the mirrored vertical velocity leaving from
  *     (x - cx, y) | zero-gradient: the value the adjacent inner row receives;
@@ -492,7 +495,12 @@ static int or_source(const or_cfg* c, const int32_t* vx, const int32_t* vy, int6
     int b = sx < 0 ? c->bc[0] : c->bc[1];
     if (b == OR_BC_PERIODIC) sx = ((sx % nx) + nx) % nx;
     else if (b == OR_BC_INLET_EQ) return 0;
-    else return or_source(c, vx, vy, sx < 0 ? x + 1 : x - 1, y, i, px, py, pj);
+    else if (b == OR_BC_OUTLET_EQ) {
+      *px = sx < 0 ? 1 : nx - 2;
+      *py = y;
+      *pj = i;
+      return 2;
+    } else return or_source(c, vx, vy, sx < 0 ? x + 1 : x - 1, y, i, px, py, pj);
   }
   if (sy < 0 || sy >= ny) {
     int b = sy < 0 ? c->bc[2] : c->bc[3];
@@ -512,6 +520,62 @@ static int or_source(const or_cfg* c, const int32_t* vx, const int32_t* vy, int6
   *py = sy;
   *pj = j;
   return 1;
+}
+
+/* Post-collision values: either a stored field (N-site planes) or, when
+   fpost is NULL, evaluated from the pre-collision field f_in at the one
+   site, with the caller's set of sites returned to quasiequilibrium. */
+typedef struct {
+  const or_cfg* c;
+  const double* fpost;
+  const double* f_in;
+  const int64_t* sel;
+  int64_t nsel;
+  double beta;
+} or_post;
+
+static double or_post_value(const or_post* P, int64_t s, int j)
+{
+  const or_cfg* c = P->c;
+  int Q = c->Q;
+  int64_t N = c->nx * c->ny;
+  if (P->fpost) return P->fpost[(int64_t)j * N + s];
+  double f[9], fs[9], M[4];
+  for (int q = 0; q < Q; ++q) f[q] = P->f_in[(int64_t)q * N + s];
+  or_moments(Q, f, M);
+  or_site_qe(c, M, fs);
+  int chosen = 0;
+  for (int64_t r = 0; r < P->nsel; ++r)
+    if (P->sel[r] == s) chosen = 1;
+  if (chosen) return fs[j];
+  double a = 2.0;
+  if (c->collision == OR_COLL_ELBM) a = or_elbm_alpha(Q, f, fs);
+  return f[j] + a * P->beta * (fs[j] - f[j]);
+}
+
+/* f_i(x, y, t+1) of a fluid site: free flight of the post-collision field
+   with the boundary rules of or_source */
+static double or_new_value(const or_post* P, const int32_t* vx, const int32_t* vy, int64_t x, int64_t y,
+                           int i)
+{
+  const or_cfg* c = P->c;
+  int64_t px, py;
+  int j;
+  int r = or_source(c, vx, vy, x, y, i, &px, &py, &j);
+  if (r == 1) return or_post_value(P, py * c->nx + px, j);
+  double fs[9];
+  if (r == 0) {
+    or_inlet_qe(c, fs);
+    return fs[i];
+  }
+  /* outlet: density and velocity of the penultimate column at t+1 */
+  double g[9], M[4];
+  for (int q = 0; q < c->Q; ++q) g[q] = or_new_value(P, vx, vy, px, py, q);
+  or_moments(c->Q, g, M);
+  double u2 = c->Q == 9 ? M[2] / M[0] : 0.0;
+  if (c->qe == OR_QE_POLY) or_qe_poly(c->Q, M[0], M[1] / M[0], u2, fs);
+  else or_qe_entropic_mm(c->Q, M[0], M[1] / M[0], u2, fs);
+  return fs[i];
 }
 
 /* f(x, 0) = quasiequilibrium of the initial fields at fluid sites, 0 in the solid */
@@ -647,21 +711,11 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS, int6
   }
 
   /* 4. free flight with boundary rules */
-  double fin_in[9];
-  or_inlet_qe(c, fin_in);
+  or_post P = {c, fpost, f_in, NULL, 0, beta};
   for (int64_t s = 0; s < N; ++s) {
     int64_t x = s % nx, y = s / nx;
-    for (int i = 0; i < Q; ++i) {
-      if (or_solid(c, x, y)) {
-        f_out[(int64_t)i * N + s] = 0.0;
-        continue;
-      }
-      int64_t px, py;
-      int j;
-      if (or_source(c, vx, vy, x, y, i, &px, &py, &j))
-        f_out[(int64_t)i * N + s] = fpost[(int64_t)j * N + py * nx + px];
-      else f_out[(int64_t)i * N + s] = fin_in[i];
-    }
+    for (int i = 0; i < Q; ++i)
+      f_out[(int64_t)i * N + s] = or_solid(c, x, y) ? 0.0 : or_new_value(&P, vx, vy, x, y, i);
   }
 
   if (dS)
@@ -684,36 +738,15 @@ int or_step_sites(const or_cfg* c, const double* f_in, const int64_t* sites, int
                   int64_t nsel, double* out)
 {
   int Q = c->Q;
-  int64_t nx = c->nx, N = c->nx * c->ny;
+  int64_t nx = c->nx;
   int32_t vx[9], vy[9];
   double w[9];
   or_velocities(Q, vx, vy, w);
-  double beta = 1.0 / (1.0 + 6.0 * c->nu);
-  double fin_in[9];
-  or_inlet_qe(c, fin_in);
+  or_post P = {c, NULL, f_in, sel, nsel, 1.0 / (1.0 + 6.0 * c->nu)};
   for (int64_t k = 0; k < ns; ++k) {
     int64_t x = sites[k] % nx, y = sites[k] / nx;
-    for (int i = 0; i < Q; ++i) {
-      double v = 0.0;
-      int64_t px, py;
-      int j;
-      if (or_solid(c, x, y)) v = 0.0;
-      else if (!or_source(c, vx, vy, x, y, i, &px, &py, &j)) v = fin_in[i];
-      else {
-        int64_t s = py * nx + px;
-        double f[9], fs[9], M[4];
-        for (int q = 0; q < Q; ++q) f[q] = f_in[(int64_t)q * N + s];
-        or_moments(Q, f, M);
-        or_site_qe(c, M, fs);
-        int chosen = 0;
-        for (int64_t r = 0; r < nsel; ++r)
-          if (sel[r] == s) chosen = 1;
-        double a = 2.0;
-        if (c->collision == OR_COLL_ELBM && !chosen) a = or_elbm_alpha(Q, f, fs);
-        v = chosen ? fs[j] : f[j] + a * beta * (fs[j] - f[j]);
-      }
-      out[k * Q + i] = v;
-    }
+    for (int i = 0; i < Q; ++i)
+      out[k * Q + i] = or_solid(c, x, y) ? 0.0 : or_new_value(&P, vx, vy, x, y, i);
   }
   return 0;
 }
@@ -728,6 +761,28 @@ double or_site_dS(const or_cfg* c, const double* f_in, int64_t site)
   or_moments(Q, f, M);
   or_site_qe(c, M, fs);
   return (double)or_delta_S(Q, f, fs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shedding frequency of a recorded signal (Sec. 4.2, Strouhal number)      */
+/* ------------------------------------------------------------------------ */
+/*
+ * power[k] = |sum_j x_j exp(-2 pi i j k / n)|^2 for k = 0 .. n/2: the
+ * discrete Fourier transform written out, summed in long double, each
+ * angle reduced exactly to 2 pi ((j k) mod n) / n.  O(n^2).
+ */
+void or_dft_power(const double* x, int64_t n, double* power)
+{
+  const long double two_pi = 6.283185307179586476925286766559L;
+  for (int64_t k = 0; k <= n / 2; ++k) {
+    long double re = 0.0L, im = 0.0L;
+    for (int64_t j = 0; j < n; ++j) {
+      long double ang = two_pi * (long double)((j * k) % n) / (long double)n;
+      re += (long double)x[j] * cosl(ang);
+      im -= (long double)x[j] * sinl(ang);
+    }
+    power[k] = (double)(re * re + im * im);
+  }
 }
 
 /* ------------------------------------------------------------------------ */

@@ -23,7 +23,7 @@ extern "C" {
 #endif
 
 enum { OR_QE_POLY = 0, OR_QE_ENTROPIC_MM = 1, OR_QE_ENTROPIC_M = 2 };
-enum { OR_BC_PERIODIC = 0, OR_BC_ZEROGRAD = 1, OR_BC_FREESLIP = 2, OR_BC_INLET_EQ = 3 };
+enum { OR_BC_PERIODIC = 0, OR_BC_ZEROGRAD = 1, OR_BC_FREESLIP = 2, OR_BC_INLET_EQ = 3, OR_BC_OUTLET_EQ = 4 };
 enum { OR_COLL_LBGK = 0, OR_COLL_ELBM = 1 };
 
 typedef struct {
@@ -77,6 +77,9 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS,
 int or_step_sites(const or_cfg* c, const double* f_in, const int64_t* sites, int64_t ns, const int64_t* sel,
                   int64_t nsel, double* out);
 double or_site_dS(const or_cfg* c, const double* f_in, int64_t site);
+
+/* power spectrum of a real signal by the DFT's definition, bins 0..n/2 */
+void or_dft_power(const double* x, int64_t n, double* power);
 
 /* MLP 4 -> 64 -> 64 -> 4 (SiLU), parameters flat (see oracle.c) */
 enum { OR_MLP_NPARAM = 4740 };

@@ -284,3 +284,99 @@ def test_elbm_reduces_to_lbgk_near_equilibrium():
         f = _near_eq_state(cfg_e, 16, amp=amp)
         d = np.abs(oracle.step(cfg_e, f)["f"] - oracle.step(cfg_l, f)["f"]).max()
         assert d < 2 * amp * amp
+
+
+def _np_step_outlet(cfg, f, Q):
+    """The outlet channel step written independently with numpy: LBGK
+    collision with the (separately pinned) polynomial quasiequilibrium,
+    free flight by numpy.roll (periodic in y), then the inlet rule at x = 0
+    and the outlet rule of Sec. 4.2 at x = nx - 1: the inward populations
+    are the quasiequilibrium at the density and velocity of the new state of
+    the penultimate column."""
+    vx, vy, _ = oracle.velocities(Q)
+    beta = 1.0 / (1.0 + 6.0 * cfg.nu)
+    ny, nx = f.shape[1:]
+    rho = f.sum(0)
+    j1 = np.tensordot(vx, f, 1)
+    j2 = np.tensordot(vy, f, 1)
+    fs = np.zeros_like(f)
+    for y in range(ny):
+        for x in range(nx):
+            fs[:, y, x] = oracle.qe_poly(Q, rho[y, x], j1[y, x] / rho[y, x], j2[y, x] / rho[y, x])
+    post = f + 2.0 * beta * (fs - f)
+    g = np.stack([np.roll(np.roll(post[i], vy[i], 0), vx[i], 1) for i in range(Q)])
+    fin = oracle.qe_poly(Q, cfg.inlet_rho, cfg.inlet_u1, cfg.inlet_u2)
+    for i in range(Q):
+        if vx[i] > 0:
+            g[i, :, 0] = fin[i]
+    pen = g[:, :, nx - 2]
+    for y in range(ny):
+        r = pen[:, y].sum()
+        fo = oracle.qe_poly(Q, r, np.dot(vx, pen[:, y]) / r, np.dot(vy, pen[:, y]) / r)
+        for i in range(Q):
+            if vx[i] < 0:
+                g[i, y, nx - 1] = fo[i]
+    return g
+
+
+@pytest.mark.parametrize("Q", [3, 9])
+def test_outlet_rule_matches_numpy_definition(Q):
+    ny = 1 if Q == 3 else 5
+    cfg = oracle.make_cfg(Q=Q, nx=9, ny=ny, nu=2e-3, bc=(W.INLET_EQ, W.OUTLET_EQ, W.PERIODIC, W.PERIODIC),
+                          inlet_rho=1.05, inlet_u=(0.04, 0.0))
+    r = np.random.default_rng(40 + Q)
+    rho = 1 + 0.1 * r.uniform(-1, 1, (ny, 9))
+    u = 0.08 * r.uniform(-1, 1, (2, ny, 9))
+    f = oracle.init(cfg, rho, u[:1] if Q == 3 else u)
+    f *= 1 + 0.03 * r.uniform(-1, 1, f.shape)
+    got = oracle.step(cfg, f)["f"]
+    want = _np_step_outlet(cfg, f, Q)
+    assert np.abs(got - want).max() <= 1e-15 * np.abs(want).max()
+    # the rule reads the new state of column nx - 2, not the old one
+    vx = oracle.velocities(Q)[0]
+    i = int(np.where(vx < 0)[0][0])
+    old = f[:, 0, 7]
+    stale = oracle.qe_poly(Q, old.sum(), np.dot(vx, old) / old.sum(), 0.0 if Q == 3 else
+                           np.dot(oracle.velocities(Q)[1], old) / old.sum())[i]
+    assert abs(got[i, 0, 8] - stale) > 1e-6
+
+
+def test_outlet_corner_and_free_slip():
+    """Corners: the x rule first (all three inward populations at the outlet
+    corner come from the penultimate column's quasiequilibrium); a uniform
+    free stream is steady with the outlet rule (poly and entropic QE)."""
+    cfg = oracle.make_cfg(Q=9, nx=10, ny=6, nu=1e-3, bc=(W.INLET_EQ, W.OUTLET_EQ, W.FREESLIP, W.FREESLIP),
+                          inlet_rho=1.0, inlet_u=(0.05, 0.0))
+    f = _near_eq_state(cfg, 41, amp=0.02)
+    g = oracle.step(cfg, f)["f"]
+    for y in (0, 5):
+        pen = g[:, y, 8]
+        fo = oracle.qe_poly(9, pen.sum(), np.dot(oracle.velocities(9)[0], pen) / pen.sum(),
+                            np.dot(oracle.velocities(9)[1], pen) / pen.sum())
+        for i in (3, 6, 7):  # W, NW, SW enter through the east face
+            assert abs(g[i, y, 9] - fo[i]) <= 1e-15
+    for qe in (oracle.QE_POLY, oracle.QE_ENTROPIC_MM):
+        c2 = oracle.make_cfg(Q=9, qe=qe, nx=12, ny=7, nu=1e-3,
+                             bc=(W.INLET_EQ, W.OUTLET_EQ, W.FREESLIP, W.FREESLIP),
+                             inlet_rho=1.0, inlet_u=(0.05, 0.0))
+        u = np.zeros((2, 7, 12))
+        u[0] = 0.05
+        f0 = oracle.init(c2, np.ones((7, 12)), u)
+        assert np.abs(oracle.run(c2, f0, 5) - f0).max() < 1e-15
+
+
+def test_outlet_in_per_site_step():
+    """The per-site step (used at full size) applies the outlet rule too."""
+    d, rho, u, _ = W.cylinder_paper(1000.0, L=4)
+    cfg = oracle.cfg_from_dict(dict(d, delta=1e-6))
+    f = oracle.init(cfg, rho, u)
+    r = np.random.default_rng(42)
+    f *= 1 + 0.02 * r.uniform(-1, 1, f.shape)
+    x0, y0, w, h = d["solid"]
+    f[:, y0:y0 + h, x0:x0 + w] = 0.0
+    out = oracle.step(cfg, f)
+    assert out["n_selected"] == d["k"]
+    nx, ny = d["nx"], d["ny"]
+    sites = np.concatenate([np.arange(ny) * nx + nx - 1, np.arange(ny) * nx + nx - 2, np.arange(0, nx * ny, 17)])
+    g = oracle.step_sites(cfg, f, sites, out["sel"])
+    assert np.array_equal(g, out["f"].reshape(9, -1)[:, sites].T)

@@ -15,7 +15,7 @@ import math
 import numpy as np
 
 # boundary-condition codes (same values as the C-ABI and the oracle)
-PERIODIC, ZEROGRAD, FREESLIP, INLET_EQ = 0, 1, 2, 3
+PERIODIC, ZEROGRAD, FREESLIP, INLET_EQ, OUTLET_EQ = 0, 1, 2, 3, 4
 QE_POLY, QE_ENTROPIC_MM, QE_ENTROPIC_M = 0, 1, 2
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
@@ -80,6 +80,32 @@ def cylinder(nx: int = 1200, ny: int = 400, side: int = 40, centre=(300, 200), u
                bc=(INLET_EQ, ZEROGRAD, FREESLIP, FREESLIP), inlet_rho=1.0, inlet_u=(u_inf, 0.0),
                solid=(x0, y0, side, side))
     return cfg, rho, u
+
+
+def cylinder_paper(re: float, L: int = 20, u_inf: float = 0.05, seed: int = 2, noise_amp: float = 1e-4,
+                   qe: int = QE_ENTROPIC_MM):
+    """The square-cylinder channel of Sec. 4.2: 30L x 25L sites, side L, centre
+    10.5L from the inlet on the centre line (solid x in [10.5L - L/2,
+    10.5L + L/2), y in [12.5L - L/2, 12.5L + L/2)); (k, delta) = (L/2, 1e-3);
+    inlet quasiequilibrium at (1, u_inf); outlet quasiequilibrium of the
+    penultimate column; free-slip walls; nu = u_inf L / Re; u = (u_inf, 0) +
+    noise_amp * xi on fluid, 0 in the solid.  Returns (cfg, rho, u, meta) with
+    meta the monitoring point (4L, -2L) from the centre and the run length
+    1250 L / u_inf."""
+    nx, ny = 30 * L, 25 * L
+    x0, y0 = (21 * L) // 2 - L // 2, ny // 2 - L // 2
+    n = nx * ny
+    rho = np.ones((ny, nx))
+    u = np.zeros((2, ny, nx))
+    u[0] = u_inf + noise_amp * noise(seed, 1, n).reshape(ny, nx)
+    u[1] = noise_amp * noise(seed, 2, n).reshape(ny, nx)
+    u[:, y0:y0 + L, x0:x0 + L] = 0.0
+    cfg = dict(Q=9, qe=qe, nx=nx, ny=ny, nu=u_inf * L / re, delta=1e-3, k=L // 2,
+               bc=(INLET_EQ, OUTLET_EQ, FREESLIP, FREESLIP), inlet_rho=1.0, inlet_u=(u_inf, 0.0),
+               solid=(x0, y0, L, L))
+    meta = dict(L=L, u_inf=u_inf, probe=(x0 + L // 2 + 4 * L, y0 + L // 2 - 2 * L),
+                t_max=int(round(1250 * L / u_inf)), window=0.25)
+    return cfg, rho, u, meta
 
 
 def shear_layer(nx: int = 8192, ny: int = 4096, seed: int = 3, nu: float = 1e-6,
@@ -158,6 +184,8 @@ CONFIGS = {
     "cylinder_1200x400_re5000": lambda: cylinder(re=5000.0),
     "cylinder_1200x400_re20000": lambda: cylinder(re=20000.0),
     "shear_8192x4096": lambda: shear_layer(),
+    "cylinder_paper_600x500_re1000": lambda: cylinder_paper(1000.0)[:3],
+    "cylinder_paper_600x500_re20000": lambda: cylinder_paper(20000.0)[:3],
     "cylinder_2400x800_re20000_fstarM": lambda: cylinder(nx=2400, ny=800, side=80, centre=(600, 400),
                                                          re=20000.0, k=256, qe=QE_ENTROPIC_M),
 }
