@@ -46,9 +46,14 @@ enum { LBM_D1Q3 = 3, LBM_D2Q9 = 9 };
    mass, momentum and energy f*_M (Sec. 2 argmax with M = (rho, rho u, 2E)) */
 enum { LBM_QE_POLY = 0, LBM_QE_ENTROPIC_MM = 1, LBM_QE_ENTROPIC_M = 2 };
 enum { LBM_FP32 = 0, LBM_FP64 = 1 };
-/* boundary rules; west/east accept PERIODIC, ZEROGRAD, INLET_EQ;
-   south/north accept PERIODIC, ZEROGRAD, FREESLIP */
-enum { LBM_BC_PERIODIC = 0, LBM_BC_ZEROGRAD = 1, LBM_BC_FREESLIP = 2, LBM_BC_INLET_EQ = 3 };
+/* boundary rules (Sec. 4.2's channel); west/east accept PERIODIC, ZEROGRAD,
+   INLET_EQ (incoming populations = quasiequilibrium of the inlet state),
+   OUTLET_EQ (incoming populations = quasiequilibrium at the density and
+   velocity of the new state of the penultimate column; needs nx >= 3 and
+   the solid clear of both columns); south/north accept PERIODIC, ZEROGRAD,
+   FREESLIP (specular reflection).  Corners take the west/east rule. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_ZEROGRAD = 1, LBM_BC_FREESLIP = 2, LBM_BC_INLET_EQ = 3,
+       LBM_BC_OUTLET_EQ = 4 };
 /* collision: LBGK (eq. lbgkLB), f' = f + 2 beta (f* - f); or ELBM
    (eq. elbmLB), f' = f + alpha beta (f* - f) with alpha the nontrivial root
    of S(f + alpha (f* - f)) = S(f) by bisection to 1e-15 (entropic
@@ -180,6 +185,38 @@ int lbm_kernel_time(lbm_ctx* ctx, double* ms, int64_t* launches);
 /* Lattice geometry actually allocated: row pitch in elements (>= nx, a
    multiple of 64) and bytes of one population buffer. */
 int lbm_layout(const lbm_ctx* ctx, int64_t* pitch, int64_t* buffer_bytes);
+
+/* ------------------------------------------------------------------------
+ * Shedding frequency (Sec. 4.2, Strouhal-Reynolds relationship): the
+ * x-velocity is recorded at a monitoring point during the run and the
+ * dominant frequency of the final quarter of the signal is taken from its
+ * discrete Fourier transform; St = L f / u_inf.
+ * ------------------------------------------------------------------------ */
+/*
+ * Monitoring point at fluid site (x, y): every later time step records the
+ * density and velocity (rho, u1, u2) of the pre-collision state f(x, t) at
+ * that site, FP64, into a ring of `capacity` samples owned by the context
+ * (24 B per sample, device memory).  Replaces a previous probe and resets
+ * its count; capacity 0 removes the probe.  LBM_E_INVAL for a site outside
+ * the lattice or in the solid, or capacity outside [0, 2^31].
+ */
+int lbm_probe_set(lbm_ctx* ctx, int64_t x, int64_t y, int64_t capacity);
+/* samples recorded since lbm_probe_set (host *total); 0 without a probe */
+int lbm_probe_count(const lbm_ctx* ctx, int64_t* total);
+/*
+ * Copies the last n samples, oldest first, into out (device double [3][n]:
+ * rho, then u1, then u2), queued on the context's stream.  n must not
+ * exceed min(count, capacity) (LBM_E_INVAL); LBM_E_STATE without a probe.
+ */
+int lbm_probe_read(lbm_ctx* ctx, double* out, int64_t n);
+/*
+ * Power spectrum of a real signal x (device double [n], 1 <= n <= 2^31):
+ * power[k] = |sum_j x_j exp(-2 pi i j k / n)|^2 for k = 0..n/2 (device
+ * double [n/2 + 1]), FP64, queued on `stream` (hipStream_t, 0: null
+ * stream).  peak (host, optional) receives the bin k >= 1 of largest power
+ * (lowest k on ties; 0 when n == 1); asking for it synchronises the stream.
+ */
+int lbm_dft_power(const double* x, int64_t n, double* power, int64_t* peak, void* stream);
 
 /* ------------------------------------------------------------------------
  * Entropic quasiequilibrium with the energy row, f*_M (Sec. 2: the

@@ -80,6 +80,8 @@ def lib():
         L.or_fstar_from_mu.argtypes = [_D, _D]
         L.or_dft_power.argtypes = [_D, C.c_int64, _D]
         L.or_dft_power.restype = None
+        L.or_dft_power_at.argtypes = [_D, C.c_int64, C.c_int64]
+        L.or_dft_power_at.restype = C.c_double
         L.or_delta_S.argtypes = [C.c_int, _D, _D]
         L.or_delta_S.restype = C.c_longdouble
         L.or_elbm_alpha.argtypes = [C.c_int, _D, _D]
@@ -263,6 +265,12 @@ def dft_power(x) -> np.ndarray:
     out = np.zeros(x.size // 2 + 1)
     lib().or_dft_power(_p(x), x.size, _p(out))
     return out
+
+
+def dft_power_at(x, bins) -> np.ndarray:
+    """dft_power at the given bins only (O(n) each)."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1)
+    return np.array([lib().or_dft_power_at(_p(x), x.size, int(k)) for k in np.asarray(bins).reshape(-1)])
 
 
 def run(cfg: _Cfg, f: np.ndarray, nsteps: int) -> np.ndarray:

@@ -769,20 +769,24 @@ double or_site_dS(const or_cfg* c, const double* f_in, int64_t site)
 /*
  * power[k] = |sum_j x_j exp(-2 pi i j k / n)|^2 for k = 0 .. n/2: the
  * discrete Fourier transform written out, summed in long double, each
- * angle reduced exactly to 2 pi ((j k) mod n) / n.  O(n^2).
+ * angle reduced exactly to 2 pi ((j k) mod n) / n.  O(n) per bin
+ * (or_dft_power_at), O(n^2) for the whole spectrum.
  */
-void or_dft_power(const double* x, int64_t n, double* power)
+double or_dft_power_at(const double* x, int64_t n, int64_t k)
 {
   const long double two_pi = 6.283185307179586476925286766559L;
-  for (int64_t k = 0; k <= n / 2; ++k) {
-    long double re = 0.0L, im = 0.0L;
-    for (int64_t j = 0; j < n; ++j) {
-      long double ang = two_pi * (long double)((j * k) % n) / (long double)n;
-      re += (long double)x[j] * cosl(ang);
-      im -= (long double)x[j] * sinl(ang);
-    }
-    power[k] = (double)(re * re + im * im);
+  long double re = 0.0L, im = 0.0L;
+  for (int64_t j = 0; j < n; ++j) {
+    long double ang = two_pi * (long double)((j * k) % n) / (long double)n;
+    re += (long double)x[j] * cosl(ang);
+    im -= (long double)x[j] * sinl(ang);
   }
+  return (double)(re * re + im * im);
+}
+
+void or_dft_power(const double* x, int64_t n, double* power)
+{
+  for (int64_t k = 0; k <= n / 2; ++k) power[k] = or_dft_power_at(x, n, k);
 }
 
 /* ------------------------------------------------------------------------ */

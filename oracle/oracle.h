@@ -80,6 +80,7 @@ double or_site_dS(const or_cfg* c, const double* f_in, int64_t site);
 
 /* power spectrum of a real signal by the DFT's definition, bins 0..n/2 */
 void or_dft_power(const double* x, int64_t n, double* power);
+double or_dft_power_at(const double* x, int64_t n, int64_t k);
 
 /* MLP 4 -> 64 -> 64 -> 4 (SiLU), parameters flat (see oracle.c) */
 enum { OR_MLP_NPARAM = 4740 };

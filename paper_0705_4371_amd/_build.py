@@ -9,7 +9,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_fstar.hip", "lbm_mlp.hip", "lbm_api_learn.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_fstar.hip", "lbm_mlp.hip", "lbm_api_learn.hip",
+           "lbm_spectrum.hip"]
 HEADERS = ["lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_internal.hpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions are generated

@@ -85,6 +85,10 @@ struct lbm_ctx {
   FstarStats* fstats = nullptr;
   FstarArgs fa{};
   int fkind = START_REST;
+  // monitoring point
+  double* probe_buf = nullptr;
+  unsigned long long* probe_n = nullptr;
+  int64_t probe_total = 0;  // samples recorded since lbm_probe_set
 };
 
 extern "C" {
@@ -150,7 +154,8 @@ int lbm_validate_config(const lbm_config* c) {
   if (c->k < 0) return fail(LBM_E_INVAL, "k must be >= 0 (got %d)", c->k);
   for (int s = 0; s < 4; ++s) {
     const int b = c->bc[s];
-    const bool ok = s < 2 ? (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_INLET_EQ)
+    const bool ok = s < 2 ? (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_INLET_EQ ||
+                             b == LBM_BC_OUTLET_EQ)
                           : (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_FREESLIP);
     if (!ok) return fail(LBM_E_INVAL, "boundary rule %d not allowed on side %d", b, s);
   }
@@ -168,12 +173,16 @@ int lbm_validate_config(const lbm_config* c) {
     if (c->qe == LBM_QE_ENTROPIC_MM && (std::fabs(c->inlet_u[0]) >= 1.0 || std::fabs(c->inlet_u[1]) >= 1.0))
       return fail(LBM_E_INVAL, "entropic inlet state needs |u_j| < 1");
   }
+  const bool out_w = c->bc[0] == LBM_BC_OUTLET_EQ, out_e = c->bc[1] == LBM_BC_OUTLET_EQ;
+  if ((out_w || out_e) && c->nx < 3) return fail(LBM_E_INVAL, "the outlet rule needs nx >= 3");
   if (c->solid_w < 0 || c->solid_h < 0) return fail(LBM_E_INVAL, "solid size must be >= 0");
   if (c->solid_w > 0 && c->solid_h > 0) {
     if (c->lattice == LBM_D1Q3) return fail(LBM_E_INVAL, "solid obstacles need D2Q9");
     if (c->solid_x0 < 0 || c->solid_y0 < 0 || c->solid_x0 + c->solid_w > c->nx ||
         c->solid_y0 + c->solid_h > c->ny)
       return fail(LBM_E_INVAL, "solid square must lie inside the lattice");
+    if ((out_w && c->solid_x0 < 2) || (out_e && c->solid_x0 + c->solid_w > c->nx - 2))
+      return fail(LBM_E_INVAL, "the solid must keep clear of an outlet column and its penultimate column");
   }
   return LBM_OK;
 }
@@ -220,7 +229,8 @@ static void ctx_release(lbm_ctx* c) {
   for (auto& e : c->ev_used) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& e : c->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   void* ptrs[] = {c->buf[0], c->buf[1], c->ctr, c->screen, c->cand, c->bnd, c->hist, c->sel, c->sel_ds,
-                  c->st, c->partials, c->Mbuf, c->mubuf, c->warm, c->fctr, c->fail_list, c->fstats};
+                  c->st, c->partials, c->Mbuf, c->mubuf, c->warm, c->fctr, c->fail_list, c->fstats,
+                  c->probe_buf, c->probe_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -294,6 +304,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   g.beta2 = 2.0 / (1.0 + 6.0 * cfg->nu);
   g.delta = cfg->delta;
   g.ds_on = std::isinf(cfg->delta) ? 0 : 1;
+  g.out_qe = cfg->qe == LBM_QE_POLY ? QE_POLY : QE_ENTROPIC_MM;
   // at most N sites can be selected: "fewer than k: all of them"
   g.kmax = (int32_t)std::min<int64_t>(cfg->k, c->N);
   // FP32 screen threshold delta (1 - 1e-2) - 64 eps32 sqrt(delta rho)
@@ -306,6 +317,8 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   a.coll = cfg->collision;
   a.Q = Q;
   a.qe = cfg->qe;
+  a.probe = -1;
+  a.probe_cap = 1;
 
   const size_t bytes = (size_t)Q * (size_t)c->plane * c->elem;
   const size_t ncap = (size_t)c->N;
@@ -459,6 +472,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       c->cur = 1 - c->cur;
       c->canonical = false;
       c->step++;
+      c->probe_total++;
       n--;
       continue;
     }
@@ -466,12 +480,14 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       if ((rc = ensure_graph(c, c->cur))) return rc;
       HIPCHK(hipGraphLaunch(c->gexec[c->cur], c->stream));
       c->step += GRAPH_STEPS;
+      c->probe_total += GRAPH_STEPS;
       n -= GRAPH_STEPS;
       continue;
     }
     HIPCHK(step_once(c, c->cur, 1 - c->cur, true, c->stream, nullptr, nullptr));
     c->cur = 1 - c->cur;
     c->step++;
+    c->probe_total++;
     n--;
   }
   return LBM_OK;
@@ -592,6 +608,100 @@ int lbm_kernel_time(lbm_ctx* c, double* ms, int64_t* launches) {
   if (rc) return rc;
   *ms = c->time_ms;
   *launches = c->launches;
+  return LBM_OK;
+}
+
+// the captured graphs hold the kernel arguments: drop them when those change
+static int drop_graphs(lbm_ctx* c) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int p = 0; p < 2; ++p) {
+    if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
+    if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+    c->gexec[p] = nullptr;
+    c->graph[p] = nullptr;
+  }
+  return LBM_OK;
+}
+
+int lbm_probe_set(lbm_ctx* c, int64_t x, int64_t y, int64_t capacity) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (capacity < 0 || capacity > ((int64_t)1 << 31))
+    return fail(LBM_E_INVAL, "capacity must be in [0, 2^31] (got %lld)", (long long)capacity);
+  const lbm_config& cf = c->cfg;
+  if (capacity > 0) {
+    if (x < 0 || x >= cf.nx || y < 0 || y >= cf.ny)
+      return fail(LBM_E_INVAL, "probe (%lld, %lld) outside the lattice", (long long)x, (long long)y);
+    if (cf.solid_w > 0 && cf.solid_h > 0 && x >= cf.solid_x0 && x < cf.solid_x0 + cf.solid_w &&
+        y >= cf.solid_y0 && y < cf.solid_y0 + cf.solid_h)
+      return fail(LBM_E_INVAL, "probe (%lld, %lld) lies in the solid", (long long)x, (long long)y);
+  }
+  int rc = drop_graphs(c);
+  if (rc) return rc;
+  if (c->probe_buf) (void)hipFree(c->probe_buf);
+  if (c->probe_n) (void)hipFree(c->probe_n);
+  c->probe_buf = nullptr;
+  c->probe_n = nullptr;
+  c->args.probe = -1;
+  c->args.probe_buf = nullptr;
+  c->args.probe_n = nullptr;
+  c->args.probe_cap = 1;
+  c->probe_total = 0;
+  if (capacity == 0) return LBM_OK;
+  if (hipMalloc((void**)&c->probe_buf, sizeof(double) * 3 * (size_t)capacity) != hipSuccess ||
+      hipMalloc((void**)&c->probe_n, sizeof(unsigned long long)) != hipSuccess) {
+    if (c->probe_buf) (void)hipFree(c->probe_buf);
+    c->probe_buf = nullptr;
+    c->probe_n = nullptr;
+    return fail(LBM_E_NOMEM, "probe buffer of %lld samples", (long long)capacity);
+  }
+  HIPCHK(hipMemsetAsync(c->probe_n, 0, sizeof(unsigned long long), c->stream));
+  HIPCHK(hipMemsetAsync(c->probe_buf, 0, sizeof(double) * 3 * (size_t)capacity, c->stream));
+  c->args.probe = x + y * cf.nx;
+  c->args.probe_buf = c->probe_buf;
+  c->args.probe_n = c->probe_n;
+  c->args.probe_cap = capacity;
+  return LBM_OK;
+}
+
+int lbm_probe_count(const lbm_ctx* c, int64_t* total) {
+  if (!c || !total) return fail(LBM_E_INVAL, "ctx and total are required");
+  *total = c->args.probe >= 0 ? c->probe_total : 0;
+  return LBM_OK;
+}
+
+int lbm_probe_read(lbm_ctx* c, double* out, int64_t n) {
+  if (!c || !out) return fail(LBM_E_INVAL, "ctx and out are required");
+  if (c->args.probe < 0) return fail(LBM_E_STATE, "no probe is set");
+  const int64_t cap = c->args.probe_cap;
+  if (n < 0 || n > std::min(c->probe_total, cap))
+    return fail(LBM_E_INVAL, "n = %lld exceeds the %lld samples held", (long long)n,
+                (long long)std::min(c->probe_total, cap));
+  if (n == 0) return LBM_OK;
+  const int64_t first = (c->probe_total - n) % cap;  // ring slot of the oldest sample wanted
+  const int64_t n1 = std::min(n, cap - first);
+  for (int comp = 0; comp < 3; ++comp) {
+    const double* src = c->probe_buf + comp * cap;
+    double* dst = out + comp * n;
+    HIPCHK(hipMemcpyAsync(dst, src + first, sizeof(double) * (size_t)n1, hipMemcpyDeviceToDevice, c->stream));
+    if (n1 < n)
+      HIPCHK(hipMemcpyAsync(dst + n1, src, sizeof(double) * (size_t)(n - n1), hipMemcpyDeviceToDevice,
+                            c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_dft_power(const double* x, int64_t n, double* power, int64_t* peak, void* stream) {
+  if (!x || !power) return fail(LBM_E_INVAL, "x and power are required");
+  if (n < 1 || n > ((int64_t)1 << 31)) return fail(LBM_E_INVAL, "n must be in [1, 2^31] (got %lld)", (long long)n);
+  hipStream_t s = (hipStream_t)stream;
+  int64_t* dpeak = nullptr;
+  if (peak && hipMalloc((void**)&dpeak, sizeof(int64_t)) != hipSuccess)
+    return fail(LBM_E_NOMEM, "peak index");
+  hipError_t e = launch_dft_power(x, n, power, dpeak, s);
+  if (e == hipSuccess && peak) e = hipMemcpyAsync(peak, dpeak, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && peak) e = hipStreamSynchronize(s);
+  if (dpeak) (void)hipFree(dpeak);
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, "dft: %s", hipGetErrorString(e));
   return LBM_OK;
 }
 

@@ -36,7 +36,7 @@ template <> struct Lat<3> {
   static __host__ __device__ constexpr double w(int i) { return i == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
 };
 
-enum : int { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_FREESLIP = 2, BC_INLET_EQ = 3 };
+enum : int { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_FREESLIP = 2, BC_INLET_EQ = 3, BC_OUTLET_EQ = 4 };
 enum : int { QE_POLY = 0, QE_ENTROPIC_MM = 1, QE_ENTROPIC_M = 2 };
 
 // Geometry and per-step parameters passed by value to every step kernel.
@@ -49,6 +49,8 @@ struct Geom {
   double delta;                  // Ehrenfests' tolerance
   int32_t ds_on;                 // 0 when delta = +inf: no Delta S work at all
   int32_t kmax;                  // k
+  int32_t out_qe;                // outlet quasiequilibrium: QE_POLY or QE_ENTROPIC_MM
+  int32_t pad0;
 };
 
 __device__ __forceinline__ bool is_solid(const Geom& g, int64_t x, int64_t y) {

@@ -37,9 +37,10 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 
 // f_i(x, y, t) from the post-collision state with the boundary rules:
 // x outside: periodic wrap | inlet quasiequilibrium | zero-gradient (the
-// value the adjacent inner column receives); y outside: periodic wrap |
-// free-slip (specular: the vertically mirrored population leaving from
-// (x - cx, y)) | zero-gradient; source in the solid: halfway bounce-back.
+// value the adjacent inner column receives) | outlet (handled by load_site;
+// never reached here); y outside: periodic wrap | free-slip (specular: the
+// vertically mirrored population leaving from (x - cx, y)) | zero-gradient;
+// source in the solid: halfway bounce-back.
 template <typename T, int Q>
 __device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g, int64_t x, int64_t y,
                                           int i) {
@@ -51,6 +52,7 @@ __device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g
       const int b = sx < 0 ? g.bc[0] : g.bc[1];
       if (b == BC_PERIODIC) sx = sx < 0 ? sx + g.nx : sx - g.nx;
       else if (b == BC_INLET_EQ) return T(g.feq_in[i]);
+      else if (b == BC_OUTLET_EQ) return T(0);
       else { x = sx < 0 ? x + 1 : x - 1; continue; }
     }
     if (sy < 0 || sy >= g.ny) {
@@ -66,10 +68,34 @@ __device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g
   return T(0);
 }
 
+// outlet rule of the channel (Sec. 4.2): the populations entering through
+// an outlet face are the quasiequilibrium at the density and velocity of the
+// new state f(xp, y, t) of the penultimate column xp
+template <typename T, int Q>
+__device__ __noinline__ void pull_outlet(const T* __restrict__ A, const Geom& g, int64_t x, int64_t xp,
+                                         int64_t y, T* f) {
+  T p[Q], fe[Q];
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) p[i] = pull_general<T, Q>(A, g, xp, y, i);
+  const Moments<Q, T> m = moments<Q, T>(p);
+  const T ux = m.jx / m.rho, uy = m.jy / m.rho;
+  if (g.out_qe == QE_POLY) qe_poly<Q, T>(m.rho, ux, uy, fe);
+  else qe_entropic_mm<Q, T>(m.rho, ux, uy, fe);
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int64_t sx = x - Lat<Q>::cx[i];
+    f[i] = (sx < 0 || sx >= g.nx) ? fe[i] : pull_general<T, Q>(A, g, x, y, i);
+  }
+}
+
 // canonical pre-collision populations of one fluid site
 template <typename T, int Q, bool PULL>
 __device__ __forceinline__ void load_site(const T* __restrict__ A, const Geom& g, int64_t x, int64_t y,
                                           T* f) {
+  if (PULL) {
+    if (x == 0 && g.bc[0] == BC_OUTLET_EQ) { pull_outlet<T, Q>(A, g, x, 1, y, f); return; }
+    if (x == g.nx - 1 && g.bc[1] == BC_OUTLET_EQ) { pull_outlet<T, Q>(A, g, x, g.nx - 2, y, f); return; }
+  }
   #pragma unroll
   for (int i = 0; i < Q; ++i)
     f[i] = PULL ? pull_general<T, Q>(A, g, x, y, i) : A[(int64_t)i * g.plane + y * g.pitch + x];
@@ -127,6 +153,16 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   }
 
   const Moments<Q, T> m = moments<Q, T>(f);
+  // monitoring point (Sec. 4.2): density and velocity of f(x, t), one sample
+  // per step into a ring (only the probe's lane ever touches it)
+  if (fluid && x + y * g.nx == a.probe) {
+    const unsigned long long n = *a.probe_n;
+    const int64_t j = (int64_t)(n % (unsigned long long)a.probe_cap);
+    a.probe_buf[j] = (double)m.rho;
+    a.probe_buf[a.probe_cap + j] = (double)m.jx / (double)m.rho;
+    a.probe_buf[2 * a.probe_cap + j] = (double)m.jy / (double)m.rho;
+    *a.probe_n = n + 1;
+  }
   T fs[Q], pb[Q];
   const T inv = inv_of(m.rho);
   const T ux = m.jx * inv, uy = m.jy * inv;

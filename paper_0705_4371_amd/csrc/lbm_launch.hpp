@@ -56,6 +56,12 @@ struct StepArgs {
   int64_t ntx, nblocks;
   int prec, Q, qe;
   int coll;  // 0 LBGK, 1 ELBM
+  // monitoring point: site index (-1: none), ring [3][probe_cap] of
+  // (rho, u1, u2) of f(x, t), and the device count of recorded samples
+  int64_t probe;
+  double* probe_buf;
+  int64_t probe_cap;
+  unsigned long long* probe_n;
 };
 
 // launch one step's kernels (fused step, rank, select, reset) on stream s;
@@ -76,6 +82,9 @@ hipError_t launch_get(const StepArgs& a, bool pull, void* out, hipStream_t s);
 hipError_t launch_set(const StepArgs& a, const void* in, hipStream_t s);
 hipError_t launch_moments(const StepArgs& a, bool pull, double* rho, double* rhou, double* e2,
                           hipStream_t s);
+// power spectrum |DFT|^2 of a real signal x[n] at bins 0..n/2 (FP64), and
+// the bin k >= 1 of largest power (lowest k on ties) into *peak (device)
+hipError_t launch_dft_power(const double* x, int64_t n, double* power, int64_t* peak, hipStream_t s);
 // FP64 conservation sums of the current pre-collision state into st->sums
 hipError_t launch_sums(const StepArgs& a, bool pull, hipStream_t s);
 hipError_t launch_clear(const StepArgs& a, hipStream_t s);

@@ -21,7 +21,7 @@ LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE, LBM_E_NOCONV, L
 LBM_D1Q3, LBM_D2Q9 = 3, 9
 LBM_QE_POLY, LBM_QE_ENTROPIC_MM, LBM_QE_ENTROPIC_M = 0, 1, 2
 LBM_FP32, LBM_FP64 = 0, 1
-LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ = 0, 1, 2, 3
+LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ, LBM_BC_OUTLET_EQ = 0, 1, 2, 3, 4
 LBM_COLL_LBGK, LBM_COLL_ELBM = 0, 1
 LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP, LBM_START_PREV = 0, 1, 2, 3
 
@@ -73,6 +73,10 @@ SIGNATURES = {
     "lbm_kernel_time": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "lbm_layout": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "lbm_struct_sizes": (None, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "lbm_probe_set": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64]),
+    "lbm_probe_count": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "lbm_probe_read": (C.c_int, [_P, _P, C.c_int64]),
+    "lbm_dft_power": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int64), _P]),
     "lbm_fstar_create": (C.c_int, [C.c_int64, _P, C.POINTER(_P)]),
     "lbm_fstar_set_tolerance": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, C.c_int32]),
     "lbm_fstar_solve": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P, _P, C.POINTER(lbm_solve_stats)]),
@@ -252,10 +256,70 @@ class Lattice:
         check(load().lbm_layout(self.ctx, C.byref(p), C.byref(b)), "lbm_layout")
         return p.value, b.value
 
+    def set_probe(self, x: int, y: int, capacity: int) -> None:
+        check(load().lbm_probe_set(self.ctx, x, y, capacity), "lbm_probe_set")
+
+    def probe_count(self) -> int:
+        n = C.c_int64()
+        check(load().lbm_probe_count(self.ctx, C.byref(n)), "lbm_probe_count")
+        return n.value
+
+    def probe_read(self, n: int):
+        """The last n probe samples, oldest first: cuda float64 [3][n] (rho, u1, u2)."""
+        t = self.torch.empty((3, n), dtype=self.torch.float64, device=self.dev)
+        check(load().lbm_probe_read(self.ctx, t.data_ptr(), n), "lbm_probe_read")
+        return t
+
 
 def _stream(stream):
     import torch
     return torch.cuda.current_stream().cuda_stream if stream is None else stream
+
+
+def dft_power(x, stream=None):
+    """|DFT|^2 of a real cuda float64 signal at bins 0..n/2 and the dominant
+    bin k >= 1 (lbm_dft_power)."""
+    import torch
+    assert x.dtype == torch.float64 and x.is_cuda and x.dim() == 1
+    x = x.contiguous()
+    power = torch.empty(x.numel() // 2 + 1, dtype=torch.float64, device=x.device)
+    peak = C.c_int64()
+    check(load().lbm_dft_power(x.data_ptr(), x.numel(), power.data_ptr(), C.byref(peak), _stream(stream)),
+          "lbm_dft_power")
+    return power, peak.value
+
+
+def strouhal(d: dict, rho0, u0, meta: dict, precision: int = LBM_FP32, steps=None, chunk: int = 20000,
+             progress=None) -> dict:
+    """Shedding frequency of the square-cylinder channel (Sec. 4.2): run
+    `steps` (default meta["t_max"] = 1250 L / u_inf) time steps recording u1
+    at the monitoring point, take the dominant DFT bin k of the final
+    meta["window"] (a quarter) of the n recorded samples, St = L (k / n) / u_inf.
+    Stops early, with st = None, when the populations become non-finite."""
+    t_max = int(steps if steps is not None else meta["t_max"])
+    n = max(2, int(round(meta["window"] * t_max)))
+    lat = Lattice(config_from_workload(d, precision), rho0, u0)
+    try:
+        lat.set_probe(meta["probe"][0], meta["probe"][1], n)
+        done, finite = 0, True
+        while done < t_max:
+            m = min(chunk, t_max - done)
+            lat.step(m)
+            done += m
+            st, _, _ = lat.stats()
+            if st.nonfinite:
+                finite = False
+                break
+            if progress:
+                progress(done, t_max, st)
+        res = dict(steps=done, finite=finite, n=n, st=None, peak=None, series=None)
+        if finite:
+            series = lat.probe_read(n)
+            _, peak = dft_power(series[1])
+            res.update(peak=peak, st=meta["L"] * (peak / n) / meta["u_inf"], series=series)
+        return res
+    finally:
+        lat.close()
 
 
 class FstarSolver:

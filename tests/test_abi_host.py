@@ -72,6 +72,10 @@ def _bad(L, **kw):
     (dict(collision=1), "ELBM needs"),
     (dict(collision=4, qe=1), "collision"),
     (dict(qe=2, lattice=3, ny=1), "D2Q9"),
+    (dict(bc=(0, 0, 4, 4)), "not allowed"),
+    (dict(nx=2, ny=4, bc=(3, 4, 2, 2)), "nx >= 3"),
+    (dict(nx=100, ny=50, bc=(3, 4, 2, 2), solid=(60, 20, 39, 5)), "clear of an outlet"),
+    (dict(nx=100, ny=50, bc=(4, 3, 2, 2), solid=(1, 20, 10, 5)), "clear of an outlet"),
 ])
 def test_invalid_configs_rejected(L, kw, frag):
     rc, msg = _bad(L, **kw)
@@ -81,7 +85,11 @@ def test_invalid_configs_rejected(L, kw, frag):
 def test_valid_configs_accepted(L):
     for kw in (dict(), dict(lattice=3, nx=800, ny=1, bc=(1, 1, 0, 0), delta=1e-3, k=4, precision=1),
                dict(nx=1200, ny=400, bc=(3, 1, 2, 2), inlet_u=(0.05, 0.0), solid=(280, 180, 40, 40),
-                    delta=1e-3, k=64)):
+                    delta=1e-3, k=64),
+               dict(nx=600, ny=500, qe=1, bc=(3, 4, 2, 2), inlet_u=(0.05, 0.0), solid=(200, 240, 20, 20),
+                    delta=1e-3, k=10),
+               dict(nx=100, ny=50, bc=(3, 4, 2, 2), solid=(60, 20, 38, 5)),
+               dict(lattice=3, nx=3, ny=1, bc=(3, 4, 0, 0))):
         rc, msg = _bad(L, **kw)
         assert rc == 0, msg
 
@@ -91,3 +99,15 @@ def test_init_rejects_null_arguments_without_gpu(L):
     out = C.c_void_p()
     assert L.load().lbm_init(C.byref(cfg), None, None, None, C.byref(out)) == L.LBM_E_INVAL
     assert L.load().lbm_step(None, 1) == L.LBM_E_INVAL
+
+
+def test_probe_and_spectrum_reject_bad_arguments_without_gpu(L):
+    lib = L.load()
+    n = C.c_int64()
+    assert lib.lbm_probe_set(None, 0, 0, 10) == L.LBM_E_INVAL
+    assert lib.lbm_probe_count(None, C.byref(n)) == L.LBM_E_INVAL
+    assert lib.lbm_probe_read(None, None, 1) == L.LBM_E_INVAL
+    buf = (C.c_double * 4)()
+    assert lib.lbm_dft_power(None, 4, buf, None, None) == L.LBM_E_INVAL
+    assert lib.lbm_dft_power(buf, 0, buf, None, None) == L.LBM_E_INVAL
+    assert lib.lbm_dft_power(buf, (1 << 31) + 1, buf, None, None) == L.LBM_E_INVAL

@@ -38,3 +38,10 @@ def test_parseval_and_shift():
     assert abs(full - n * np.dot(x, x)) <= 1e-12 * n * np.dot(x, x)
     q = oracle.dft_power(np.roll(x, 123))
     assert np.abs(p - q).max() <= 1e-12 * p.max()
+
+
+def test_single_bin_equals_spectrum():
+    x = np.random.default_rng(9).standard_normal(301)
+    p = oracle.dft_power(x)
+    bins = [0, 1, 17, 150]
+    assert np.array_equal(oracle.dft_power_at(x, bins), p[bins])
