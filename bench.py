@@ -115,6 +115,42 @@ def cylinder_leg(args, torch, lbm, W, net):
     return out
 
 
+def active_leg(args, torch, lbm, lat, n_sites):
+    """The same lattice with an outbreak of non-equilibrium: populations of a
+    band of `rows` rows multiplied by 1 + 0.05 xi (xi uniform in [-1, 1),
+    seeded), so that Delta S > delta at about 10^6 sites per step and the
+    ranking, top-k selection (k = 4096 of n >> k) and reset run at full load.
+    Timed over `steps` steps (whole step, wall clock)."""
+    import numpy as np
+    f = lat.get_populations()
+    rows = args.active_rows
+    y0 = (lat.cfg.ny - rows) // 2
+    r = np.random.default_rng(11)
+    band = torch.from_numpy(1 + 0.05 * r.uniform(-1, 1, (lat.Q, rows, lat.cfg.nx))).to(f.dtype).cuda()
+    f[:, y0:y0 + rows, :] *= band
+    lat.set_populations(f)
+    del f, band
+    lat.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    above = 0
+    sel = 0
+    chunk = 10
+    for _ in range(args.active_steps // chunk):
+        lat.step(chunk)
+        st, _, _ = lat.stats()
+        above += st.n_above_delta
+        sel += st.n_selected
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nsamp = args.active_steps // chunk
+    steps = nsamp * chunk
+    return {"band_rows": rows, "steps": steps, "MLUPS": round(n_sites * steps / dt / 1e6, 1),
+            "ms_per_step": round(dt * 1e3 / steps, 4),
+            "mean_n_above_delta": round(above / nsamp, 1), "mean_n_selected": round(sel / nsamp, 1),
+            "note": "wall clock including one statistics read-back every %d steps" % chunk}
+
+
 def fstar_leg(args, torch, lbm, W):
     """Entropic f*_M solve on the 4096 x 2048 moment field: the warm-start MLP
     is trained on 2^24 (moments, multipliers) pairs produced by the solver
@@ -198,6 +234,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-fstar", action="store_true", help="skip the f*_M / MLP leg")
+    ap.add_argument("--no-active", action="store_true", help="skip the leg with many sites above delta")
+    ap.add_argument("--active-rows", type=int, default=256)
+    ap.add_argument("--active-steps", type=int, default=200)
     ap.add_argument("--no-cylinder", action="store_true", help="skip the f*_M cylinder run")
     ap.add_argument("--cyl-steps", type=int, default=2000)
     ap.add_argument("--fx", type=int, default=4096)
@@ -298,6 +337,9 @@ def main():
                       "mass": st.mass},
         "graph_replay_MLUPS": round(n_sites * args.steps / dt_graph / 1e6, 1),
     }
+    if not args.no_active:
+        print("# Ehrenfests' steps at full load", file=sys.stderr, flush=True)
+        out["ehrenfest_active"] = active_leg(args, torch, lbm, lat, n_sites)
     lat.close()
     if not args.no_fstar:
         print("# f*_M leg", file=sys.stderr, flush=True)

@@ -72,7 +72,7 @@ __device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g
 // an outlet face are the quasiequilibrium at the density and velocity of the
 // new state f(xp, y, t) of the penultimate column xp
 template <typename T, int Q>
-__device__ __noinline__ void pull_outlet(const T* __restrict__ A, const Geom& g, int64_t x, int64_t xp,
+__device__ __forceinline__ void pull_outlet(const T* __restrict__ A, const Geom& g, int64_t x, int64_t xp,
                                          int64_t y, T* f) {
   T p[Q], fe[Q];
   #pragma unroll
@@ -222,8 +222,10 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
     if (scr) a.screen[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(x + y * g.nx);
   }
 
-  // sticky flag for non-finite populations (a non-finite f gives a non-finite rho)
-  if (__ballot(fluid && !__builtin_isfinite(m.rho)) && (threadIdx.x & 63) == 0)
+  // sticky flag for non-finite populations (a non-finite f gives a non-finite
+  // rho); once it is set, waves only read it (no atomic storm on one word)
+  if (__ballot(fluid && !__builtin_isfinite(m.rho)) && (threadIdx.x & 63) == 0 &&
+      __atomic_load_n(&a.ctr[C_NONFINITE], __ATOMIC_RELAXED) == 0u)
     atomicOr(&a.ctr[C_NONFINITE], 1u);
 }
 
@@ -260,12 +262,29 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
       qe_eval<Q, QE, double>(m, fs);
     }
     const double ds = dS_fp64<Q>(fd, fs);
-    if (ds > g.delta) {
-      const uint32_t idx = atomicAdd(&a.ctr[C_CAND], 1u);
-      a.cand[idx] = Cand{site, 0u, ds};
-      const unsigned long long bits = (unsigned long long)__double_as_longlong(ds);
-      atomicAdd(&a.hist[(bits >> 48) & (HIST_BINS - 1)], 1u);
-      if (__builtin_isinf(ds)) atomicAdd(&a.ctr[C_INVALID], 1u);
+    const bool is_c = ds > g.delta;
+    // append with one counter atomic per wavefront; histogram atomics are
+    // merged for the lanes that share the leader's bin (an outbreak of
+    // invalid sites puts every one of them in the +inf bin)
+    const unsigned long long mask = __ballot(is_c);
+    if (mask) {
+      const int lane = threadIdx.x & 63;
+      const int leader = __ffsll((long long)mask) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&a.ctr[C_CAND], (uint32_t)__popcll(mask));
+      base = (uint32_t)__shfl((int)base, leader);
+      const uint32_t bin = (uint32_t)(((unsigned long long)__double_as_longlong(ds) >> 48) & (HIST_BINS - 1));
+      const uint32_t lbin = (uint32_t)__shfl((int)bin, leader);
+      const unsigned long long same = __ballot(is_c && bin == lbin);
+      const unsigned long long inv = __ballot(is_c && __builtin_isinf(ds));
+      if (is_c) {
+        a.cand[base + __popcll(mask & ((1ull << lane) - 1ull))] = Cand{site, 0u, ds};
+        if (bin != lbin) atomicAdd(&a.hist[bin], 1u);
+      }
+      if (lane == leader) {
+        atomicAdd(&a.hist[lbin], (uint32_t)__popcll(same));
+        if (inv) atomicAdd(&a.ctr[C_INVALID], (uint32_t)__popcll(inv));
+      }
     }
   }
 }

@@ -289,13 +289,14 @@ def dft_power(x, stream=None):
     return power, peak.value
 
 
-def strouhal(d: dict, rho0, u0, meta: dict, precision: int = LBM_FP32, steps=None, chunk: int = 20000,
+def strouhal(d: dict, rho0, u0, meta: dict, precision: int = LBM_FP32, steps=None, chunk: int = 2000,
              progress=None) -> dict:
     """Shedding frequency of the square-cylinder channel (Sec. 4.2): run
     `steps` (default meta["t_max"] = 1250 L / u_inf) time steps recording u1
     at the monitoring point, take the dominant DFT bin k of the final
     meta["window"] (a quarter) of the n recorded samples, St = L (k / n) / u_inf.
-    Stops early, with st = None, when the populations become non-finite."""
+    Stops early, with st = None, when the populations become non-finite
+    (checked every `chunk` steps; progress(step, t_max, stats) is called then)."""
     t_max = int(steps if steps is not None else meta["t_max"])
     n = max(2, int(round(meta["window"] * t_max)))
     lat = Lattice(config_from_workload(d, precision), rho0, u0)

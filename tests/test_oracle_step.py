@@ -367,7 +367,7 @@ def test_outlet_corner_and_free_slip():
 
 def test_outlet_in_per_site_step():
     """The per-site step (used at full size) applies the outlet rule too."""
-    d, rho, u, _ = W.cylinder_paper(1000.0, L=4)
+    d, rho, u, _ = W.cylinder_paper(1000.0, L=4, outlet=W.OUTLET_EQ)
     cfg = oracle.cfg_from_dict(dict(d, delta=1e-6))
     f = oracle.init(cfg, rho, u)
     r = np.random.default_rng(42)

@@ -83,14 +83,15 @@ def cylinder(nx: int = 1200, ny: int = 400, side: int = 40, centre=(300, 200), u
 
 
 def cylinder_paper(re: float, L: int = 20, u_inf: float = 0.05, seed: int = 2, noise_amp: float = 1e-4,
-                   qe: int = QE_ENTROPIC_MM):
+                   qe: int = QE_ENTROPIC_MM, outlet: int = ZEROGRAD):
     """The square-cylinder channel of Sec. 4.2: 30L x 25L sites, side L, centre
     10.5L from the inlet on the centre line (solid x in [10.5L - L/2,
     10.5L + L/2), y in [12.5L - L/2, 12.5L + L/2)); (k, delta) = (L/2, 1e-3);
-    inlet quasiequilibrium at (1, u_inf); outlet quasiequilibrium of the
-    penultimate column; free-slip walls; nu = u_inf L / Re; u = (u_inf, 0) +
-    noise_amp * xi on fluid, 0 in the solid.  Returns (cfg, rho, u, meta) with
-    meta the monitoring point (4L, -2L) from the centre and the run length
+    inlet quasiequilibrium at (1, u_inf); outlet zero-gradient (default) or
+    OUTLET_EQ, the paper's quasiequilibrium of the penultimate column;
+    free-slip walls; nu = u_inf L / Re; u = (u_inf, 0) + noise_amp * xi on
+    fluid, 0 in the solid.  Returns (cfg, rho, u, meta) with meta the
+    monitoring point (4L, -2L) from the centre and the run length
     1250 L / u_inf."""
     nx, ny = 30 * L, 25 * L
     x0, y0 = (21 * L) // 2 - L // 2, ny // 2 - L // 2
@@ -101,7 +102,7 @@ def cylinder_paper(re: float, L: int = 20, u_inf: float = 0.05, seed: int = 2, n
     u[1] = noise_amp * noise(seed, 2, n).reshape(ny, nx)
     u[:, y0:y0 + L, x0:x0 + L] = 0.0
     cfg = dict(Q=9, qe=qe, nx=nx, ny=ny, nu=u_inf * L / re, delta=1e-3, k=L // 2,
-               bc=(INLET_EQ, OUTLET_EQ, FREESLIP, FREESLIP), inlet_rho=1.0, inlet_u=(u_inf, 0.0),
+               bc=(INLET_EQ, outlet, FREESLIP, FREESLIP), inlet_rho=1.0, inlet_u=(u_inf, 0.0),
                solid=(x0, y0, L, L))
     meta = dict(L=L, u_inf=u_inf, probe=(x0 + L // 2 + 4 * L, y0 + L // 2 - 2 * L),
                 t_max=int(round(1250 * L / u_inf)), window=0.25)
