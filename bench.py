@@ -19,7 +19,6 @@ Prints one JSON line:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -32,14 +31,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar_dev.hpp"):
-        with open(os.path.join(ROOT, "paper_0705_4371_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profile(workload: str, prec: str, n_sites: int):
     """HBM bytes per k_step launch from the committed rocprofv3 PMC summary,
     or None if the summary is missing or the kernel source changed since."""
@@ -48,6 +39,7 @@ def traffic_from_profile(workload: str, prec: str, n_sites: int):
         return None
     with open(path) as fh:
         d = json.load(fh)
+    from paper_0705_4371_amd.profiling import kernel_source_hash
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
     return d.get("hbm_bytes_per_launch")

@@ -1,0 +1,130 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+- ``stats``: the kernel statistics of a ``rocprofv3 --kernel-trace --stats``
+  run (``*_kernel_stats.csv``) as a markdown table, with the command that
+  produced it.
+- ``pmc``: HBM traffic of one kernel per dispatch from two counter runs
+  (``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``, KiB per dispatch), each
+  scaled by what the same counter reads for a plain device copy of known
+  size (the copy's bytes divided by its counter reading), as JSON.  The JSON
+  records the hash of the step kernel's sources (``kernel_source_hash``) so
+  that a reader can tell when the counters no longer describe the kernel.
+
+Usage (from the repository root):
+  python -m paper_0705_4371_amd.profiling stats DIR --command "..." --title "..."
+  python -m paper_0705_4371_amd.profiling pmc --kernel k_step --fetch DIR --write DIR \\
+      --copy-fetch DIR --copy-write DIR --algorithmic-bytes B --workload "..." --command "..."
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+STEP_SOURCES = ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar_dev.hpp")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources the fused step kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_0705_4371_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _one(pattern: str) -> str:
+    hits = sorted(glob.glob(pattern, recursive=True))
+    if not hits:
+        raise FileNotFoundError(pattern)
+    return hits[0]
+
+
+def _rows(path: str) -> list:
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def stats_markdown(directory: str, command: str, title: str, top: int = 30) -> str:
+    rows = _rows(_one(os.path.join(directory, "**", "*kernel_stats.csv")))
+    out = ["# %s" % title, "", "Command (repository root REPO on the GPU machine, after "
+           "`cd /tmp && export TMPDIR=/tmp`):", "", "    " + command, "",
+           "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("|", "\\|")
+        if len(name) > 90:
+            name = name[:90] + "..."
+        out.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f%% |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def counter_per_dispatch(directory: str, kernel: str, counter: str, skip_first: int = 0):
+    """Mean counter value (KiB) over the dispatches whose name contains `kernel`."""
+    rows = _rows(_one(os.path.join(directory, "**", "*counter_collection.csv")))
+    vals = [float(r["Counter_Value"]) for r in rows
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    vals = vals[skip_first:]
+    if not vals:
+        raise ValueError("no %s dispatches of %s in %s" % (counter, kernel, directory))
+    return sum(vals) / len(vals), len(vals)
+
+
+def pmc_summary(a) -> dict:
+    fetch, nf = counter_per_dispatch(a.fetch, a.kernel_match, "FETCH_SIZE", a.skip_first)
+    write, nw = counter_per_dispatch(a.write, a.kernel_match, "WRITE_SIZE", a.skip_first)
+    cf, _ = counter_per_dispatch(a.copy_fetch, a.copy_kernel, "FETCH_SIZE")
+    cw, _ = counter_per_dispatch(a.copy_write, a.copy_kernel, "WRITE_SIZE")
+    copy_bytes = float(a.copy_bytes)
+    ff, fw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    rd, wr = fetch * 1024.0 * ff, write * 1024.0 * fw
+    return {
+        "kernel": a.kernel, "workload": a.workload, "kernel_source_hash": kernel_source_hash(),
+        "fetch_size_kib_per_dispatch": round(fetch, 1), "write_size_kib_per_dispatch": round(write, 1),
+        "dispatches_averaged": min(nf, nw),
+        "copy_calibration": {"what": a.copy_what, "fetch_size_kib": cf, "write_size_kib": cw,
+                             "fetch_factor": round(ff, 5), "write_factor": round(fw, 5)},
+        "hbm_read_bytes_per_launch": int(rd), "hbm_write_bytes_per_launch": int(wr),
+        "hbm_bytes_per_launch": int(rd + wr), "algorithmic_bytes_per_launch": int(a.algorithmic_bytes),
+        "ratio_to_algorithmic": round((rd + wr) / float(a.algorithmic_bytes), 5),
+        "commands": a.command,
+    }
+
+
+def main(argv=None) -> None:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--command", required=True)
+    s.add_argument("--title", required=True)
+    p = sub.add_parser("pmc")
+    p.add_argument("--kernel", required=True, help="name written into the summary")
+    p.add_argument("--kernel-match", required=True, help="substring of the dispatch name")
+    p.add_argument("--fetch", required=True)
+    p.add_argument("--write", required=True)
+    p.add_argument("--copy-fetch", required=True)
+    p.add_argument("--copy-write", required=True)
+    p.add_argument("--copy-kernel", default="copyBuffer")
+    p.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    p.add_argument("--copy-what", default="torch copy of 2^28 float32 (1 GiB read, 1 GiB written)")
+    p.add_argument("--algorithmic-bytes", type=float, required=True)
+    p.add_argument("--workload", required=True)
+    p.add_argument("--skip-first", type=int, default=0)
+    p.add_argument("--command", action="append", required=True)
+    a = ap.parse_args(argv)
+    if a.what == "stats":
+        sys.stdout.write(stats_markdown(a.dir, a.command, a.title))
+    else:
+        json.dump(pmc_summary(a), sys.stdout, indent=1)
+        sys.stdout.write("\n")
+
+
+if __name__ == "__main__":
+    main()
