@@ -509,7 +509,7 @@ int lbm_set_populations(lbm_ctx* c, const void* f) {
   c->canonical = true;
   c->step = 0;
   c->nonfinite_seen = false;
-  if (flags[C_NONFINITE + 2]) {
+  if (flags[C_SETBAD]) {
     c->nonfinite_seen = true;
     return fail(LBM_E_NONFINITE, "populations hold non-finite values");
   }

@@ -112,6 +112,26 @@ __device__ __forceinline__ void fstar_from_mu_buf(const double* __restrict__ mu,
   }
 }
 
+// block-wide exclusive offset of `flag` and one global atomic per block on
+// *counter; s_cnt: 4 words of LDS; returns the slot of a flagged lane
+__device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter, uint32_t* s_cnt,
+                                                 uint32_t* s_base) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const unsigned long long mask = __ballot(flag);
+  if (lane == 0) s_cnt[w] = (uint32_t)__popcll(mask);
+  __syncthreads();
+  if (tid == 0) {
+    const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    *s_base = tot ? atomicAdd(counter, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t base = *s_base;
+  for (int v = 0; v < w; ++v) base += s_cnt[v];
+  const uint32_t slot = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+  __syncthreads();  // s_cnt / s_base are reused by the next call
+  return slot;
+}
+
 // ---------------------------------------------------------------------------
 // k_step
 // ---------------------------------------------------------------------------
@@ -211,15 +231,11 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
     for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = f[i] + b2 * (fs[i] - f[i]);
   }
 
-  // append screened sites: one atomic per wavefront
-  const unsigned long long mask = __ballot(scr);
-  if (mask) {
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&a.ctr[C_SCREEN], (uint32_t)__popcll(mask));
-    base = (uint32_t)__shfl((int)base, leader);
-    if (scr) a.screen[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)(x + y * g.nx);
+  // append screened sites: one atomic per workgroup that has any
+  if (__syncthreads_or(scr)) {
+    __shared__ uint32_t s_cnt[4], s_base;
+    const uint32_t slot = block_append(scr, &a.ctr[C_SCREEN], s_cnt, &s_base);
+    if (scr) a.screen[slot] = (uint32_t)(x + y * g.nx);
   }
 
   // sticky flag for non-finite populations (a non-finite f gives a non-finite
@@ -230,143 +246,267 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// k_rank: FP64 Delta S of screened sites
-// ---------------------------------------------------------------------------
-template <typename T, int Q, int QE, bool PULL>
-__global__ __launch_bounds__(256) void k_rank(StepArgs a) {
-  const T* __restrict__ A = (const T*)a.A;
-  const Geom& g = a.g;
-  const uint32_t n = a.ctr[C_SCREEN];
-  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
-    const uint32_t site = a.screen[t];
-    const int64_t y = site / g.nx, x = site - y * g.nx;
-    T fT[Q];
-    load_site<T, Q, PULL>(A, g, x, y, fT);
-    double fd[Q];
-    #pragma unroll
-    for (int i = 0; i < Q; ++i) fd[i] = (double)fT[i];
-    const Moments<Q, double> m = moments<Q, double>(fd);
-    double fs[Q];
-    if constexpr (QE == QE_ENTROPIC_M) {
-      // the solver's multipliers polished to FP64 round-off for the ranking
-      const int64_t N = g.nx * g.ny;
-      const double mus[4] = {a.mu[site], a.mu[N + site], a.mu[2 * N + site], a.mu[3 * N + site]};
-      const double ir = 1.0 / m.rho;
-      if (feasible(m.rho, m.jx * ir, m.jy * ir, m.e2 * ir)) {
-        const FS<double> p = polish64(mus, m.rho, m.jx * ir, m.jy * ir, m.e2 * ir, 3);
-        fstar_pop<double>(m.rho * p.a, p.X, p.Y, p.Z, fs);
-      } else {
-        fstar_pop<double>(::exp(mus[0]), ::exp(mus[1]), ::exp(mus[2]), ::exp(mus[3]), fs);
-      }
-    } else {
-      qe_eval<Q, QE, double>(m, fs);
-    }
-    const double ds = dS_fp64<Q>(fd, fs);
-    const bool is_c = ds > g.delta;
-    // append with one counter atomic per wavefront; histogram atomics are
-    // merged for the lanes that share the leader's bin (an outbreak of
-    // invalid sites puts every one of them in the +inf bin)
-    const unsigned long long mask = __ballot(is_c);
-    if (mask) {
-      const int lane = threadIdx.x & 63;
-      const int leader = __ffsll((long long)mask) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&a.ctr[C_CAND], (uint32_t)__popcll(mask));
-      base = (uint32_t)__shfl((int)base, leader);
-      const uint32_t bin = (uint32_t)(((unsigned long long)__double_as_longlong(ds) >> 48) & (HIST_BINS - 1));
-      const uint32_t lbin = (uint32_t)__shfl((int)bin, leader);
-      const unsigned long long same = __ballot(is_c && bin == lbin);
-      const unsigned long long inv = __ballot(is_c && __builtin_isinf(ds));
-      if (is_c) {
-        a.cand[base + __popcll(mask & ((1ull << lane) - 1ull))] = Cand{site, 0u, ds};
-        if (bin != lbin) atomicAdd(&a.hist[bin], 1u);
-      }
-      if (lane == leader) {
-        atomicAdd(&a.hist[lbin], (uint32_t)__popcll(same));
-        if (inv) atomicAdd(&a.ctr[C_INVALID], (uint32_t)__popcll(inv));
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// k_select: at most k candidates, largest Delta S first, ties by lower site
+// Ranking and selection (Sec. 3.2: at most k sites with Delta S > delta,
+// the largest first, ties by lower site index)
 // ---------------------------------------------------------------------------
 // Key of a candidate: the 63 bits of its non-negative FP64 Delta S followed
 // by the 32 bits of ~site (a larger key = larger Delta S, then lower site).
 // Keys are unique, so "the k largest keys" is one well-defined set.
+//   k_rank      FP64 Delta S of the screened sites; candidates are appended
+//               with one atomic per workgroup; a 2^15-bin histogram of the
+//               top key bits is built (in LDS per workgroup when many sites
+//               are screened); when more than k sites were screened, the
+//               last workgroup to finish finds the bin b* holding the k-th
+//               largest key and how many keys r to take from it.
+//   k_partition candidates above b* (or all of them, if there are at most k)
+//               are selected and returned to quasiequilibrium at once;
+//               candidates in b* go to a boundary list.
+//   k_refine    one workgroup: 8-bit radix passes over the boundary list find
+//               the r largest keys there, which are selected and reset; the
+//               statistics are written and the counters cleared.
 __device__ __forceinline__ unsigned long long ds_bits(double d) {
   return (unsigned long long)__double_as_longlong(d);
 }
 
-__global__ __launch_bounds__(1024) void k_select(StepArgs a) {
-  __shared__ uint32_t s_scan[1024];
-  __shared__ uint32_t s_hist[256];
-  __shared__ uint32_t s_nsel, s_nbnd, s_bstar, s_r, s_dig, s_rr, s_exact;
-  __shared__ double s_max[16], s_min[16];
-  const int tid = threadIdx.x;
-  const uint32_t n = a.ctr[C_CAND];
+__device__ __forceinline__ uint32_t ds_bin(double d) {
+  return (uint32_t)(ds_bits(d) >> 48) & (HIST_BINS - 1);
+}
+
+// return one selected site to quasiequilibrium: re-pull f(x, t) from the
+// state A, the same f* as k_step, written over the collided values in B
+template <typename T, int Q, int QE, bool PULL>
+__device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
+  const T* __restrict__ A = (const T*)a.A;
+  T* __restrict__ B = (T*)a.B;
+  const Geom& g = a.g;
+  const int64_t y = site / g.nx, x = site - y * g.nx;
+  T fs[Q];
+  if constexpr (QE == QE_ENTROPIC_M) {
+    fstar_from_mu_buf<T>(a.mu, g.nx * g.ny, site, fs);
+  } else {
+    T f[Q];
+    load_site<T, Q, PULL>(A, g, x, y, f);
+    const Moments<Q, T> m = moments<Q, T>(f);
+    qe_eval<Q, QE, T>(m, fs);
+  }
+  const int64_t o = y * g.pitch + x;
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = fs[i];
+}
+
+constexpr int RANK_BLOCKS = 512;
+constexpr uint32_t LDS_HIST_MIN = 16384;  // screened sites above which the histogram is built in LDS
+constexpr uint32_t SEL_ALL = 0xFFFFFFFFu;  // b* value: every candidate is selected
+
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(256) void k_rank(StepArgs a) {
+  __shared__ uint32_t s_hist[HIST_BINS / 2];  // two 16-bit counts per word
+  __shared__ uint32_t s_cnt[4], s_base, s_inv[4];
+  __shared__ int s_last;
+  uint32_t* s_scan = s_hist;  // reused after the histogram is flushed
+  const T* __restrict__ A = (const T*)a.A;
+  const Geom& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t n = a.ctr[C_SCREEN];
+  const uint32_t k = (uint32_t)g.kmax;
+  // with at most k screened sites every candidate is selected: no histogram
+  const bool need_hist = k > 0 && n > k;
+  const bool lds = need_hist && n > LDS_HIST_MIN;
+  if (lds) {
+    for (int j = tid; j < HIST_BINS / 2; j += 256) s_hist[j] = 0u;
+    __syncthreads();
+  }
+  uint32_t it = 0;
+  // the trip count is uniform over the workgroup (block barriers inside)
+  for (uint32_t t0 = blockIdx.x * 256u; t0 < n; t0 += gridDim.x * 256u) {
+    const uint32_t t = t0 + tid;
+    bool is_c = false;
+    double ds = 0.0;
+    uint32_t site = 0;
+    if (t < n) {
+      site = a.screen[t];
+      const int64_t y = site / g.nx, x = site - y * g.nx;
+      T fT[Q];
+      load_site<T, Q, PULL>(A, g, x, y, fT);
+      double fd[Q];
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) fd[i] = (double)fT[i];
+      const Moments<Q, double> m = moments<Q, double>(fd);
+      double fs[Q];
+      if constexpr (QE == QE_ENTROPIC_M) {
+        // the solver's multipliers polished to FP64 round-off for the ranking
+        const int64_t N = g.nx * g.ny;
+        const double mus[4] = {a.mu[site], a.mu[N + site], a.mu[2 * N + site], a.mu[3 * N + site]};
+        const double ir = 1.0 / m.rho;
+        if (feasible(m.rho, m.jx * ir, m.jy * ir, m.e2 * ir)) {
+          const FS<double> p = polish64(mus, m.rho, m.jx * ir, m.jy * ir, m.e2 * ir, 3);
+          fstar_pop<double>(m.rho * p.a, p.X, p.Y, p.Z, fs);
+        } else {
+          fstar_pop<double>(::exp(mus[0]), ::exp(mus[1]), ::exp(mus[2]), ::exp(mus[3]), fs);
+        }
+      } else {
+        qe_eval<Q, QE, double>(m, fs);
+      }
+      ds = dS_fp64<Q>(fd, fs);
+      is_c = ds > g.delta;
+    }
+    const uint32_t slot = block_append(is_c, &a.ctr[C_CAND], s_cnt, &s_base);
+    const uint32_t bin = ds_bin(ds);
+    const unsigned long long inv = __ballot(is_c && __builtin_isinf(ds));
+    if (lane == 0) s_inv[w] = (uint32_t)__popcll(inv);
+    if (lds) {
+      if (is_c) atomicAdd(&s_hist[bin >> 1], 1u << (16 * (bin & 1u)));
+    } else if (need_hist) {
+      // global histogram: lanes that share the wave leader's bin are merged
+      const unsigned long long mask = __ballot(is_c);
+      if (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        const uint32_t lbin = (uint32_t)__shfl((int)bin, leader);
+        const unsigned long long same = __ballot(is_c && bin == lbin);
+        if (is_c && bin != lbin) atomicAdd(&a.hist[bin], 1u);
+        if (lane == leader) atomicAdd(&a.hist[lbin], (uint32_t)__popcll(same));
+      }
+    }
+    if (is_c) a.cand[slot] = Cand{site, 0u, ds};
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t ni = s_inv[0] + s_inv[1] + s_inv[2] + s_inv[3];
+      if (ni) atomicAdd(&a.ctr[C_INVALID], ni);
+    }
+    // flushed every 128 iterations: at most 128 x 256 = 32768 keys per
+    // 16-bit count
+    if (lds && (++it & 127u) == 0u) {
+      __syncthreads();
+      for (int j = tid; j < HIST_BINS / 2; j += 256) {
+        const uint32_t v = s_hist[j];
+        if (v & 0xFFFFu) atomicAdd(&a.hist[2 * j], v & 0xFFFFu);
+        if (v >> 16) atomicAdd(&a.hist[2 * j + 1], v >> 16);
+        s_hist[j] = 0u;
+      }
+      __syncthreads();
+    }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int j = tid; j < HIST_BINS / 2; j += 256) {
+      const uint32_t v = s_hist[j];
+      if (v & 0xFFFFu) atomicAdd(&a.hist[2 * j], v & 0xFFFFu);
+      if (v >> 16) atomicAdd(&a.hist[2 * j + 1], v >> 16);
+    }
+  }
+  if (!need_hist) return;
+
+  // the last workgroup to finish locates b* (the histogram is complete)
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&a.ctr[C_DONE], 1u) == gridDim.x - 1u;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const uint32_t nc = __atomic_load_n(&a.ctr[C_CAND], __ATOMIC_RELAXED);
+  if (nc <= k) {
+    if (tid == 0) { a.ctr[C_BSTAR] = SEL_ALL; a.ctr[C_R] = 0u; a.ctr[C_DONE] = 0u; }
+    return;
+  }
+  // thread t owns the 128 bins [HIST_BINS-1-128t-127, HIST_BINS-1-128t], top first
+  __syncthreads();
+  uint32_t local = 0;
+  for (int j = 0; j < 128; ++j) local += __atomic_load_n(&a.hist[HIST_BINS - 1 - 128 * tid - j], __ATOMIC_RELAXED);
+  s_scan[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
+    __syncthreads();
+    s_scan[tid] += v;
+    __syncthreads();
+  }
+  const uint32_t incl = s_scan[tid], excl = incl - local;
+  if (excl < k && incl >= k) {
+    uint32_t c = excl;
+    for (int j = 0; j < 128; ++j) {
+      const uint32_t b = HIST_BINS - 1 - 128 * tid - j;
+      const uint32_t h = __atomic_load_n(&a.hist[b], __ATOMIC_RELAXED);
+      if (c + h >= k) { a.ctr[C_BSTAR] = b; a.ctr[C_R] = k - c; break; }
+      c += h;
+    }
+  }
+  if (tid == 0) a.ctr[C_DONE] = 0u;
+}
+
+constexpr int PART_BLOCKS = 256;
+
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(256) void k_partition(StepArgs a) {
+  __shared__ uint32_t s_cnt[4], s_base;
+  __shared__ unsigned long long s_mx[4], s_mn[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t nc = a.ctr[C_CAND];
+  const uint32_t n = a.ctr[C_SCREEN];
   const uint32_t k = (uint32_t)a.g.kmax;
-  double vmax = 0.0, vmin = __builtin_inf();
-  if (tid == 0) { s_nsel = 0; s_nbnd = 0; s_bstar = 0; s_r = 0; }
+  if (nc == 0) return;
+  const bool all = k == 0 || n <= k || a.ctr[C_BSTAR] == SEL_ALL;
+  const uint32_t bstar = all ? 0u : a.ctr[C_BSTAR];
+  unsigned long long mx = 0ull, mn = ~0ull;
+  for (uint32_t t0 = blockIdx.x * 256u; t0 < nc; t0 += gridDim.x * 256u) {
+    const uint32_t t = t0 + tid;
+    Cand c{0u, 0u, 0.0};
+    if (t < nc) c = a.cand[t];
+    const uint32_t bin = ds_bin(c.ds);
+    const bool take = t < nc && k > 0 && (all || bin > bstar);
+    const bool bnd = t < nc && !all && k > 0 && bin == bstar;
+    if (t < nc) mx = ds_bits(c.ds) > mx ? ds_bits(c.ds) : mx;
+    if (take) mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
+    const uint32_t s1 = block_append(take, &a.ctr[C_NSEL0], s_cnt, &s_base);
+    const uint32_t s2 = block_append(bnd, &a.ctr[C_NBND], s_cnt, &s_base);
+    if (take) {
+      a.sel[s1] = c.site;
+      a.sel_ds[s1] = c.ds;
+      reset_site<T, Q, QE, PULL>(a, c.site);
+    }
+    if (bnd) a.bnd[s2] = c;
+  }
+  // workgroup max of all candidates and min of the selected ones
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long ox = (unsigned long long)__shfl_xor((long long)mx, off);
+    const unsigned long long on = (unsigned long long)__shfl_xor((long long)mn, off);
+    mx = ox > mx ? ox : mx;
+    mn = on < mn ? on : mn;
+  }
+  if (lane == 0) { s_mx[w] = mx; s_mn[w] = mn; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int v = 1; v < 4; ++v) {
+      mx = s_mx[v] > mx ? s_mx[v] : mx;
+      mn = s_mn[v] < mn ? s_mn[v] : mn;
+    }
+    mx = s_mx[0] > mx ? s_mx[0] : mx;
+    mn = s_mn[0] < mn ? s_mn[0] : mn;
+    if (mx) atomicMax(&a.st->max_bits, mx);
+    if (mn != ~0ull) atomicMin(&a.st->min_bits, mn);
+  }
+}
+
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(1024) void k_refine(StepArgs a) {
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_nsel, s_dig, s_rr, s_exact;
+  __shared__ unsigned long long s_mn[16];
+  const int tid = threadIdx.x;
+  const uint32_t nc = a.ctr[C_CAND];
+  const uint32_t n = a.ctr[C_SCREEN];
+  const uint32_t k = (uint32_t)a.g.kmax;
+  const bool all = k == 0 || n <= k || nc <= k || a.ctr[C_BSTAR] == SEL_ALL;
+  const uint32_t nsel0 = a.ctr[C_NSEL0];
+  const uint32_t m = a.ctr[C_NBND];
+  unsigned long long mn = ~0ull;
+  if (tid == 0) s_nsel = 0;
   __syncthreads();
 
-  if (k == 0 || n <= k) {
-    for (uint32_t t = tid; t < n; t += 1024) {
-      const Cand c = a.cand[t];
-      vmax = fmax(vmax, c.ds);
-      if (k > 0) {
-        a.sel[t] = c.site;
-        a.sel_ds[t] = c.ds;
-        vmin = fmin(vmin, c.ds);
-      }
-    }
-    if (tid == 0) s_nsel = k > 0 ? n : 0;
-  } else {
-    // 1. the histogram bin that holds the k-th largest key; thread t owns
-    //    the 32 bins [HIST_BINS-1-32t-31, HIST_BINS-1-32t], top first
-    uint32_t local = 0;
-    for (int j = 0; j < 32; ++j) local += a.hist[HIST_BINS - 1 - 32 * tid - j];
-    s_scan[tid] = local;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
-      __syncthreads();
-      s_scan[tid] += v;
-      __syncthreads();
-    }
-    const uint32_t incl = s_scan[tid], excl = incl - local;
-    if (excl < k && incl >= k) {
-      uint32_t c = excl;
-      for (int j = 0; j < 32; ++j) {
-        const uint32_t bin = HIST_BINS - 1 - 32 * tid - j;
-        const uint32_t h = a.hist[bin];
-        if (c + h >= k) { s_bstar = bin; s_r = k - c; break; }
-        c += h;
-      }
-    }
-    __syncthreads();
-    const uint32_t bstar = s_bstar;
-
-    // 2. keys in higher bins are selected; keys in the bin are refined
-    for (uint32_t t = tid; t < n; t += 1024) {
-      const Cand c = a.cand[t];
-      vmax = fmax(vmax, c.ds);
-      const uint32_t bin = (uint32_t)(ds_bits(c.ds) >> 48) & (HIST_BINS - 1);
-      if (bin > bstar) {
-        const uint32_t i = atomicAdd(&s_nsel, 1u);
-        if (i < k) { a.sel[i] = c.site; a.sel_ds[i] = c.ds; }
-        vmin = fmin(vmin, c.ds);
-      } else if (bin == bstar) {
-        a.bnd[atomicAdd(&s_nbnd, 1u)] = c;
-      }
-    }
-    __syncthreads();
-    const uint32_t m = s_nbnd;
-
-    // 3. 8-bit digits of the remaining key: Delta S bits 47..0, then ~site
+  if (nc > 0 && !all) {
+    // 8-bit digits of the remaining key below the histogram bits: Delta S
+    // bits 47..0, then ~site; rr keys are still to be taken
     unsigned long long Thi = 0, Mhi = 0;
-    uint32_t Tlo = 0, Mlo = 0, rr = s_r;
+    uint32_t Tlo = 0, Mlo = 0, rr = a.ctr[C_R];
     for (int pass = 0; pass < 10; ++pass) {
       const bool inhi = pass < 6;
       const int sh = inhi ? 40 - 8 * pass : 24 - 8 * (pass - 6);
@@ -399,73 +539,53 @@ __global__ __launch_bounds__(1024) void k_select(StepArgs a) {
       __syncthreads();
       if (done) break;
     }
-
-    // 4. keys of the bin that are >= T (T's unfixed low bits are zero)
+    // keys of the bin that are >= T (T's unfixed low bits are zero)
     for (uint32_t t = tid; t < m; t += 1024) {
       const Cand c = a.bnd[t];
       const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
       const uint32_t lo = ~c.site;
       if (hi > Thi || (hi == Thi && lo >= Tlo)) {
-        const uint32_t i = atomicAdd(&s_nsel, 1u);
-        if (i < k) { a.sel[i] = c.site; a.sel_ds[i] = c.ds; }
-        vmin = fmin(vmin, c.ds);
+        const uint32_t i = nsel0 + atomicAdd(&s_nsel, 1u);
+        if (i < k) {
+          a.sel[i] = c.site;
+          a.sel_ds[i] = c.ds;
+          reset_site<T, Q, QE, PULL>(a, c.site);
+        }
+        mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
       }
     }
   }
-
-  // block max / min
-  #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    vmax = fmax(vmax, __shfl_xor(vmax, off));
-    vmin = fmin(vmin, __shfl_xor(vmin, off));
+    const unsigned long long on = (unsigned long long)__shfl_xor((long long)mn, off);
+    mn = on < mn ? on : mn;
   }
-  if ((tid & 63) == 0) { s_max[tid >> 6] = vmax; s_min[tid >> 6] = vmin; }
+  if ((tid & 63) == 0) s_mn[tid >> 6] = mn;
   __syncthreads();
   if (tid == 0) {
-    double mx = 0.0, mn = __builtin_inf();
-    for (int w = 0; w < 16; ++w) { mx = fmax(mx, s_max[w]); mn = fmin(mn, s_min[w]); }
-    const uint32_t nsel = s_nsel < k ? s_nsel : k;  // == k by construction
-    a.st->n_above = n;
+    for (int v = 0; v < 16; ++v) mn = s_mn[v] < mn ? s_mn[v] : mn;
+    const unsigned long long pm = a.st->min_bits;
+    mn = pm < mn ? pm : mn;
+    const uint32_t nsel = k == 0 ? 0u : (nc < k ? nc : k);
+    a.st->n_above = nc;
     a.st->n_sel = nsel;
     a.st->n_invalid = a.ctr[C_INVALID];
     a.st->total_sel += nsel;
-    a.st->max = n ? mx : 0.0;
-    a.st->kth = nsel ? mn : 0.0;
-    a.ctr[C_NSEL] = nsel;
+    a.st->max = nc ? __longlong_as_double((long long)a.st->max_bits) : 0.0;
+    a.st->kth = nsel ? __longlong_as_double((long long)mn) : 0.0;
+    a.st->max_bits = 0ull;
+    a.st->min_bits = ~0ull;
     a.ctr[C_SCREEN] = 0;
     a.ctr[C_CAND] = 0;
     a.ctr[C_INVALID] = 0;
+    a.ctr[C_NSEL0] = 0;
+    a.ctr[C_NBND] = 0;
+    a.ctr[C_BSTAR] = 0;
+    a.ctr[C_R] = 0;
   }
-  // clear the histogram for the next step
-  if (n > 0)
+  // clear the histogram for the next step (k_rank fills it only when more
+  // than k sites were screened)
+  if (nc > 0 && k > 0 && n > k)
     for (int j = tid; j < HIST_BINS; j += 1024) a.hist[j] = 0;
-}
-
-// ---------------------------------------------------------------------------
-// k_reset: Ehrenfests' step at the selected sites
-// ---------------------------------------------------------------------------
-template <typename T, int Q, int QE, bool PULL>
-__global__ __launch_bounds__(64) void k_reset(StepArgs a) {
-  const uint32_t n = a.ctr[C_NSEL];
-  const uint32_t t = blockIdx.x * 64u + threadIdx.x;
-  if (t >= n) return;
-  const T* __restrict__ A = (const T*)a.A;
-  T* __restrict__ B = (T*)a.B;
-  const Geom& g = a.g;
-  const uint32_t site = a.sel[t];
-  const int64_t y = site / g.nx, x = site - y * g.nx;
-  T fs[Q];
-  if constexpr (QE == QE_ENTROPIC_M) {
-    fstar_from_mu_buf<T>(a.mu, g.nx * g.ny, site, fs);
-  } else {
-    T f[Q];
-    load_site<T, Q, PULL>(A, g, x, y, f);
-    const Moments<Q, T> m = moments<Q, T>(f);
-    qe_eval<Q, QE, T>(m, fs);
-  }
-  const int64_t o = y * g.pitch + x;
-  #pragma unroll
-  for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = fs[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -527,7 +647,7 @@ __global__ __launch_bounds__(256) void k_set(StepArgs a, const T* __restrict__ i
       S[(int64_t)i * g.plane + y * g.pitch + x] = v;
     }
   }
-  if (bad) atomicOr(&a.ctr[C_NONFINITE + 2], 1u);
+  if (bad) atomicOr(&a.ctr[C_SETBAD], 1u);
 }
 
 template <typename T, int Q, bool PULL>
@@ -615,6 +735,8 @@ __global__ __launch_bounds__(256) void k_clear(StepArgs a) {
   if (t0 == 0) {
     a.st->n_above = a.st->n_sel = a.st->n_invalid = a.st->total_sel = 0;
     a.st->kth = a.st->max = 0.0;
+    a.st->max_bits = 0ull;
+    a.st->min_bits = ~0ull;
     for (int c = 0; c < 4; ++c) a.st->sums[c] = 0.0;
   }
 }
@@ -696,10 +818,9 @@ static hipError_t step_t(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEv
     hipLaunchKernelGGL((k_step<T, Q, QE, PULL>), dim3((unsigned)a.nblocks), dim3(STEP_TX), 0, s, a);
   if (ev1) { hipError_t e = hipEventRecord(ev1, s); if (e != hipSuccess) return e; }
   if (a.g.ds_on) {
-    hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(512), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, a);
-    if (a.g.kmax > 0)
-      hipLaunchKernelGGL((k_reset<T, Q, QE, PULL>), dim3((unsigned)((a.g.kmax + 63) / 64)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_partition<T, Q, QE, PULL>), dim3(PART_BLOCKS), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(1024), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -21,6 +21,7 @@ struct DevStats {
   unsigned long long n_above, n_sel, n_invalid, total_sel;
   double kth, max;
   double sums[4];
+  unsigned long long max_bits, min_bits;  // running max / min of Delta S bit patterns (>= 0)
 };
 
 // device counters (uint32 each)
@@ -29,8 +30,13 @@ enum : int {
   C_CAND = 1,      // sites with FP64 Delta S > delta this step
   C_INVALID = 2,   // candidates with Delta S = +inf
   C_NONFINITE = 3, // sticky: a non-finite moment sum was seen
-  C_NSEL = 4,      // sites selected this step (read by the reset kernel)
-  C_COUNT = 8
+  C_NSEL0 = 4,     // sites selected by k_partition (above the bin b*)
+  C_SETBAD = 5,    // set_populations met a non-finite value
+  C_DONE = 6,      // k_rank workgroups finished (last one finds b*)
+  C_BSTAR = 7,     // histogram bin holding the k-th largest key, or SEL_ALL
+  C_R = 8,         // keys still to take from bin b*
+  C_NBND = 9,      // candidates in bin b* (boundary list)
+  C_COUNT = 16
 };
 
 constexpr int HIST_BITS = 15;
