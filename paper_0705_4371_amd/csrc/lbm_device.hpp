@@ -41,7 +41,7 @@ enum : int { QE_POLY = 0, QE_ENTROPIC_MM = 1, QE_ENTROPIC_M = 2 };
 
 // Geometry and per-step parameters passed by value to every step kernel.
 struct Geom {
-  int64_t nx, ny, pitch, plane;  // plane = pitch * ny elements
+  int64_t nx, ny, pitch, plane;  // pitch = nx rounded up to 64; plane = pitch * ny elements
   int32_t bc[4];                 // west, east, south, north
   int64_t sx0, sy0, sx1, sy1;    // solid square [sx0, sx1) x [sy0, sy1); empty if sx1 <= sx0
   double feq_in[9];              // inlet quasiequilibrium (FP64; cast at use)
@@ -52,6 +52,16 @@ struct Geom {
   int32_t out_qe;                // outlet quasiequilibrium: QE_POLY or QE_ENTROPIC_MM
   int32_t pad0;
 };
+
+// State layout: tiles of 64 sites of one row.  Population i of site (x, y)
+// lives at ((y * (pitch / 64) + x / 64) * Q + i) * 64 + x % 64, so a
+// wavefront's 64 sites read each population as one contiguous run and the Q
+// runs of a tile are adjacent (fewer concurrent DRAM streams than Q separate
+// planes).  x must lie in [0, pitch).
+template <int Q>
+__device__ __forceinline__ int64_t sidx(const Geom& g, int64_t x, int64_t y, int i) {
+  return ((y * (g.pitch >> 6) + (x >> 6)) * Q + i) * 64 + (x & 63);
+}
 
 __device__ __forceinline__ bool is_solid(const Geom& g, int64_t x, int64_t y) {
   return x >= g.sx0 && x < g.sx1 && y >= g.sy0 && y < g.sy1;

@@ -14,11 +14,12 @@
 //   k_reset  selected sites: re-pull f(x, t), recompute f*, overwrite the
 //            collided values with f* (return to quasiequilibrium).
 //
-// State layout: population planes [Q][ny][pitch] of T (float or double),
-// x fastest, pitch a multiple of 64 elements.  The state buffer holds the
-// post-collision populations f'(x, t-1) at their origin site ("pull"
-// layout); right after init or set_populations it holds the pre-collision
-// f(x, t) itself ("canonical" layout) and the first step reads it in place.
+// State layout: tiles of 64 sites of a row, [ny][pitch/64][Q][64] of T
+// (float or double), pitch = nx rounded up to 64 (see sidx).  The state
+// buffer holds the post-collision populations f'(x, t-1) at their origin
+// site ("pull" layout); right after init or set_populations it holds the
+// pre-collision f(x, t) itself ("canonical" layout) and the first step reads
+// it in place.
 #include <hip/hip_runtime.h>
 
 #include "lbm_device.hpp"
@@ -63,7 +64,7 @@ __device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g
       else { y = sy < 0 ? y + 1 : y - 1; continue; }
     }
     if (is_solid(g, sx, sy)) { j = Lat<Q>::opp[i]; sx = x; sy = y; }
-    return A[(int64_t)j * g.plane + sy * g.pitch + sx];
+    return A[sidx<Q>(g, sx, sy, j)];
   }
   return T(0);
 }
@@ -98,7 +99,7 @@ __device__ __forceinline__ void load_site(const T* __restrict__ A, const Geom& g
   }
   #pragma unroll
   for (int i = 0; i < Q; ++i)
-    f[i] = PULL ? pull_general<T, Q>(A, g, x, y, i) : A[(int64_t)i * g.plane + y * g.pitch + x];
+    f[i] = PULL ? pull_general<T, Q>(A, g, x, y, i) : A[sidx<Q>(g, x, y, i)];
 }
 
 // f*_M populations of site s from the multiplier buffer mu [4][N]
@@ -154,10 +155,8 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
     const bool yin = (Q == 3) || (y >= 1 && y <= g.ny - 2);
     const bool hit = x0 - 1 < g.sx1 && x0 + STEP_TX >= g.sx0 && y - 1 < g.sy1 && y + 1 >= g.sy0;
     if (xin && yin && !hit) {
-      const int64_t o = y * g.pitch + x;
       #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        f[i] = A[(int64_t)i * g.plane + o - Lat<Q>::cy[i] * g.pitch - Lat<Q>::cx[i]];
+      for (int i = 0; i < Q; ++i) f[i] = A[sidx<Q>(g, x - Lat<Q>::cx[i], y - Lat<Q>::cy[i], i)];
     } else if (fluid) {
       load_site<T, Q, true>(A, g, x, y, f);
     } else {
@@ -226,9 +225,8 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
       for (int i = 0; i < Q; ++i) { fd[i] = (double)f[i]; fsd[i] = (double)fs[i]; }
       b2 = T(0.5 * g.beta2 * elbm_alpha<Q>(fd, fsd));
     }
-    const int64_t o = y * g.pitch + x;
     #pragma unroll
-    for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = f[i] + b2 * (fs[i] - f[i]);
+    for (int i = 0; i < Q; ++i) B[sidx<Q>(g, x, y, i)] = f[i] + b2 * (fs[i] - f[i]);
   }
 
   // append screened sites: one atomic per workgroup that has any
@@ -289,9 +287,8 @@ __device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
     const Moments<Q, T> m = moments<Q, T>(f);
     qe_eval<Q, QE, T>(m, fs);
   }
-  const int64_t o = y * g.pitch + x;
   #pragma unroll
-  for (int i = 0; i < Q; ++i) B[(int64_t)i * g.plane + o] = fs[i];
+  for (int i = 0; i < Q; ++i) B[sidx<Q>(g, x, y, i)] = fs[i];
 }
 
 constexpr int RANK_BLOCKS = 512;
@@ -609,7 +606,7 @@ __global__ __launch_bounds__(256) void k_init(StepArgs a, const double* __restri
       else qe_entropic_mm<Q, double>(rho, ux, uy, fs);
     }
     #pragma unroll
-    for (int i = 0; i < Q; ++i) S[(int64_t)i * g.plane + y * g.pitch + x] = (T)fs[i];
+    for (int i = 0; i < Q; ++i) S[sidx<Q>(g, x, y, i)] = (T)fs[i];
   }
 }
 
@@ -644,7 +641,7 @@ __global__ __launch_bounds__(256) void k_set(StepArgs a, const T* __restrict__ i
     for (int i = 0; i < Q; ++i) {
       const T v = in[(int64_t)i * N + s];
       bad |= !__builtin_isfinite(v);
-      S[(int64_t)i * g.plane + y * g.pitch + x] = v;
+      S[sidx<Q>(g, x, y, i)] = v;
     }
   }
   if (bad) atomicOr(&a.ctr[C_SETBAD], 1u);
@@ -802,7 +799,7 @@ __global__ __launch_bounds__(256) void k_init_M_pops(StepArgs a) {
       fstar_pop<double>(::exp(a.mu[s]), ::exp(a.mu[N + s]), ::exp(a.mu[2 * N + s]), ::exp(a.mu[3 * N + s]), fs);
     }
     #pragma unroll
-    for (int i = 0; i < 9; ++i) S[(int64_t)i * g.plane + y * g.pitch + x] = (T)fs[i];
+    for (int i = 0; i < 9; ++i) S[sidx<9>(g, x, y, i)] = (T)fs[i];
   }
 }
 
