@@ -217,6 +217,7 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
 
   // LBGK collision f' = f + 2 beta (f* - f) (eq. (lbgkLB)), or ELBM
   // f' = f + alpha beta (f* - f) (eq. (elbmLB)); written at the origin site
+  // with non-temporal stores (nothing reads it again in this step)
   if (fluid) {
     T b2 = T(g.beta2);
     if constexpr (ELBM) {
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
       b2 = T(0.5 * g.beta2 * elbm_alpha<Q>(fd, fsd));
     }
     #pragma unroll
-    for (int i = 0; i < Q; ++i) B[sidx<Q>(g, x, y, i)] = f[i] + b2 * (fs[i] - f[i]);
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(T(f[i] + b2 * (fs[i] - f[i])), &B[sidx<Q>(g, x, y, i)]);
   }
 
   // append screened sites: one atomic per workgroup that has any
