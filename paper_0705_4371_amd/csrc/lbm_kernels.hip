@@ -133,6 +133,31 @@ __device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter, u
   return slot;
 }
 
+// f(x, t) of lane x of the row segment [x0, x0 + STEP_TX) of row y: segments
+// whose whole 3 x (STEP_TX + 2) neighbourhood is inside the lattice and clear
+// of the solid pull directly (a uniform branch per block); other fluid sites
+// take the boundary rules; non-fluid lanes get the rest weights (unused)
+template <typename T, int Q, bool PULL>
+__device__ __forceinline__ void load_segment_site(const T* __restrict__ A, const Geom& g, int64_t x0, int64_t x,
+                                                  int64_t y, bool fluid, T* f) {
+  if (PULL) {
+    const bool xin = x0 >= 1 && x0 + STEP_TX <= g.nx - 1;
+    const bool yin = (Q == 3) || (y >= 1 && y <= g.ny - 2);
+    const bool hit = x0 - 1 < g.sx1 && x0 + STEP_TX >= g.sx0 && y - 1 < g.sy1 && y + 1 >= g.sy0;
+    if (xin && yin && !hit) {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = A[sidx<Q>(g, x - Lat<Q>::cx[i], y - Lat<Q>::cy[i], i)];
+      return;
+    }
+  }
+  if (fluid) {
+    load_site<T, Q, PULL>(A, g, x, y, f);
+  } else {
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = T(Lat<Q>::w(i));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_step
 // ---------------------------------------------------------------------------
@@ -148,28 +173,7 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   const bool fluid = x < g.nx && !is_solid(g, x, y);
 
   T f[Q];
-  if (PULL) {
-    // tiles whose whole 3 x (STEP_TX + 2) neighbourhood is inside the lattice
-    // and clear of the solid pull directly (uniform branch per block)
-    const bool xin = x0 >= 1 && x0 + STEP_TX <= g.nx - 1;
-    const bool yin = (Q == 3) || (y >= 1 && y <= g.ny - 2);
-    const bool hit = x0 - 1 < g.sx1 && x0 + STEP_TX >= g.sx0 && y - 1 < g.sy1 && y + 1 >= g.sy0;
-    if (xin && yin && !hit) {
-      #pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = A[sidx<Q>(g, x - Lat<Q>::cx[i], y - Lat<Q>::cy[i], i)];
-    } else if (fluid) {
-      load_site<T, Q, true>(A, g, x, y, f);
-    } else {
-      #pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = T(Lat<Q>::w(i));
-    }
-  } else {
-    if (fluid) load_site<T, Q, false>(A, g, x, y, f);
-    else {
-      #pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = T(Lat<Q>::w(i));
-    }
-  }
+  load_segment_site<T, Q, PULL>(A, g, x0, x, y, fluid, f);
 
   const Moments<Q, T> m = moments<Q, T>(f);
   // monitoring point (Sec. 4.2): density and velocity of f(x, t), one sample
@@ -682,11 +686,11 @@ template <typename T, int Q, bool PULL>
 __global__ __launch_bounds__(256) void k_sums(StepArgs a) {
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
-  const int64_t N = g.nx * g.ny;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-    const int64_t y = i / g.nx, x = i - y * g.nx;
-    if (is_solid(g, x, y)) continue;
+  // sites in layout order (a wavefront covers one 64-site tile)
+  for (int64_t p = blockIdx.x * 256ll + threadIdx.x; p < g.plane; p += (int64_t)gridDim.x * 256) {
+    const int64_t y = p / g.pitch, x = p - y * g.pitch;
+    if (x >= g.nx || is_solid(g, x, y)) continue;
     T f[Q];
     load_site<T, Q, PULL>(A, g, x, y, f);
     double fd[Q];
@@ -743,30 +747,35 @@ __global__ __launch_bounds__(256) void k_clear(StepArgs a) {
 // f*_M support: moments for the solver, initial state from the multipliers
 // ---------------------------------------------------------------------------
 template <typename T, bool PULL>
-__global__ __launch_bounds__(256) void k_moments_M(StepArgs a) {
+__global__ __launch_bounds__(STEP_TX) void k_moments_M(StepArgs a) {
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
   const int64_t N = g.nx * g.ny;
-  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
-    const int64_t y = s / g.nx, x = s - y * g.nx;
-    double r = 1.0, jx = 0.0, jy = 0.0, e2 = 2.0 / 3.0;
-    if (!is_solid(g, x, y)) {
-      T f[9];
-      load_site<T, 9, PULL>(A, g, x, y, f);
-      double fd[9];
-      #pragma unroll
-      for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
-      const Moments<9, double> m = moments<9, double>(fd);
-      r = m.rho;
-      jx = m.jx;
-      jy = m.jy;
-      e2 = m.e2;
-    }
-    a.Mbuf[s] = r;
-    a.Mbuf[N + s] = jx;
-    a.Mbuf[2 * N + s] = jy;
-    a.Mbuf[3 * N + s] = e2;
+  // the row segments of k_step (same interior fast path)
+  const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
+  const int64_t y = b / a.ntx;
+  const int64_t x0 = (b - y * a.ntx) * STEP_TX;
+  const int64_t x = x0 + threadIdx.x;
+  const bool fluid = x < g.nx && !is_solid(g, x, y);
+  T f[9];
+  load_segment_site<T, 9, PULL>(A, g, x0, x, y, fluid, f);
+  if (x >= g.nx) return;
+  double r = 1.0, jx = 0.0, jy = 0.0, e2 = 2.0 / 3.0;
+  if (fluid) {
+    double fd[9];
+    #pragma unroll
+    for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
+    const Moments<9, double> m = moments<9, double>(fd);
+    r = m.rho;
+    jx = m.jx;
+    jy = m.jy;
+    e2 = m.e2;
   }
+  const int64_t s = x + y * g.nx;
+  a.Mbuf[s] = r;
+  a.Mbuf[N + s] = jx;
+  a.Mbuf[2 * N + s] = jy;
+  a.Mbuf[3 * N + s] = e2;
 }
 
 __global__ __launch_bounds__(256) void k_init_M_moments(StepArgs a, const double* __restrict__ rho0,
@@ -920,7 +929,7 @@ hipError_t launch_sums(const StepArgs& a, bool pull, hipStream_t s) {
 }
 
 hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s) {
-  const unsigned gr = site_grid(a);
+  const unsigned gr = (unsigned)a.nblocks;
   if (a.prec == 1) {
     if (pull) hipLaunchKernelGGL((k_moments_M<double, true>), dim3(gr), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_moments_M<double, false>), dim3(gr), dim3(256), 0, s, a);

@@ -53,15 +53,17 @@ __device__ __forceinline__ bf16x8 load8(const float* p) {
 }
 
 // weight operands of the three layers for this lane
-struct Weights {
+struct Mats {
   bf16x8 w1[4];     // layer 1, unit tile t: W1[16t + r][k], k < 4 real
   bf16x8 w2[4][2];  // layer 2, unit tile t, k step kk: W2[16t + r][32kk + 8g + j]
   bf16x8 w3[2];     // layer 3, k step kk: W3[r][32kk + 8g + j], r < 4 real
+};
+struct Weights : Mats {
   float b1[4][4], b2[4][4];  // bias of unit 16t + 4g + j
   float b3[4];               // bias of output j (lanes g == 0)
 };
 
-__device__ void load_weights(const float* __restrict__ p, int r, int g, Weights& w) {
+__device__ void load_mats(const float* __restrict__ p, int r, int g, Mats& w) {
   #pragma unroll
   for (int t = 0; t < 4; ++t) {
     bf16x8 v = zero8();
@@ -72,6 +74,15 @@ __device__ void load_weights(const float* __restrict__ p, int r, int g, Weights&
     w.w1[t] = v;
     #pragma unroll
     for (int kk = 0; kk < 2; ++kk) w.w2[t][kk] = load8(p + MLP_OW2 + (16 * t + r) * 64 + 32 * kk + 8 * g);
+  }
+  #pragma unroll
+  for (int kk = 0; kk < 2; ++kk) w.w3[kk] = r < 4 ? load8(p + MLP_OW3 + r * 64 + 32 * kk + 8 * g) : zero8();
+}
+
+__device__ void load_weights(const float* __restrict__ p, int r, int g, Weights& w) {
+  load_mats(p, r, g, w);
+  #pragma unroll
+  for (int t = 0; t < 4; ++t) {
     #pragma unroll
     for (int j = 0; j < 4; ++j) {
       w.b1[t][j] = p[MLP_OB1 + 16 * t + 4 * g + j];
@@ -79,10 +90,24 @@ __device__ void load_weights(const float* __restrict__ p, int r, int g, Weights&
     }
   }
   #pragma unroll
-  for (int kk = 0; kk < 2; ++kk) w.w3[kk] = r < 4 ? load8(p + MLP_OW3 + r * 64 + 32 * kk + 8 * g) : zero8();
-  #pragma unroll
   for (int j = 0; j < 4; ++j) w.b3[j] = g == 0 ? p[MLP_OB3 + j] : 0.0f;
 }
+
+// bias access for forward16: the lane's registers (training) or a per-block
+// LDS copy (inference, which keeps fewer registers live)
+struct RegBias {
+  const Weights& w;
+  __device__ float b1(int t, int j) const { return w.b1[t][j]; }
+  __device__ float b2(int t, int j) const { return w.b2[t][j]; }
+  __device__ float b3(int j) const { return w.b3[j]; }
+};
+struct LdsBias {
+  const float* p;  // the 4740 parameters' bias entries copied to LDS: b1 [64], b2 [64], b3 [4]
+  int g;
+  __device__ float b1(int t, int j) const { return p[16 * t + 4 * g + j]; }
+  __device__ float b2(int t, int j) const { return p[64 + 16 * t + 4 * g + j]; }
+  __device__ float b3(int j) const { return g == 0 ? p[128 + j] : 0.0f; }
+};
 
 // Epoch shuffle: position i of the epoch reads sample perm(i), perm a
 // pseudo-random bijection of [0, n): a 4-round Feistel network on 2h bits
@@ -122,9 +147,23 @@ constexpr int TROW = 40;
 // hold the 4 BF16 features of sample r).  Hs1/Hs2: this wave's site-major
 // LDS tiles [16][SROW].  z1/z2 (optional) receive the pre-activations in the
 // D layout; y receives the output (lanes g == 0, outputs 0..3 of sample r).
-template <bool KEEP>
-__device__ __forceinline__ void forward16(const Weights& w, bf16x8 xin, __bf16* Hs1, __bf16* Hs2, int r, int g,
-                                          f32x4* z1, f32x4* z2, f32x4& y) {
+// sync: per-wave tiles need only the wave's own LDS order (SYNC_WAVE), the
+// training kernel's single-wave blocks use a block barrier
+enum { SYNC_BLOCK = 0, SYNC_WAVE = 1 };
+template <int SYNC>
+__device__ __forceinline__ void tile_sync() {
+  if constexpr (SYNC == SYNC_WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <bool KEEP, int SYNC = SYNC_BLOCK, class Bias = RegBias>
+__device__ __forceinline__ void forward16(const Mats& w, const Bias& bias, bf16x8 xin, __bf16* Hs1, __bf16* Hs2,
+                                          int r, int g, f32x4* z1, f32x4* z2, f32x4& y) {
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -132,13 +171,13 @@ __device__ __forceinline__ void forward16(const Weights& w, bf16x8 xin, __bf16* 
     bf16x4 h;
     #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float z = d[j] + w.b1[t][j];
+      const float z = d[j] + bias.b1(t, j);
       if (KEEP) z1[t][j] = z;
       h[j] = (__bf16)silu(z);
     }
     *(bf16x4*)(Hs1 + r * SROW + 16 * t + 4 * g) = h;
   }
-  __syncthreads();
+  tile_sync<SYNC>();
   bf16x8 b2[2];
   #pragma unroll
   for (int kk = 0; kk < 2; ++kk) b2[kk] = *(const bf16x8*)(Hs1 + r * SROW + 32 * kk + 8 * g);
@@ -149,47 +188,53 @@ __device__ __forceinline__ void forward16(const Weights& w, bf16x8 xin, __bf16* 
     bf16x4 h;
     #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float z = d[j] + w.b2[t][j];
+      const float z = d[j] + bias.b2(t, j);
       if (KEEP) z2[t][j] = z;
       h[j] = (__bf16)silu(z);
     }
     *(bf16x4*)(Hs2 + r * SROW + 16 * t + 4 * g) = h;
   }
-  __syncthreads();
+  tile_sync<SYNC>();
   bf16x8 b3[2];
   #pragma unroll
   for (int kk = 0; kk < 2; ++kk) b3[kk] = *(const bf16x8*)(Hs2 + r * SROW + 32 * kk + 8 * g);
   f32x4 d = mfma(w.w3[0], b3[0], zero);
   d = mfma(w.w3[1], b3[1], d);
   #pragma unroll
-  for (int j = 0; j < 4; ++j) y[j] = d[j] + w.b3[j];
+  for (int j = 0; j < 4; ++j) y[j] = d[j] + bias.b3(j);
 }
 
 // ---------------------------------------------------------------------------
 // inference
 // ---------------------------------------------------------------------------
-// Each wave takes tiles of 16 samples; the block's 4 waves step through
-// their tiles in lock step so that block barriers can order the LDS traffic.
+// Each wave takes tiles of 16 samples on its own (its LDS tiles are private,
+// so only the wave's own LDS order matters); the biases sit in LDS, shared by
+// the block, which keeps fewer registers live per lane.
 template <bool WARM>
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ params, const float* __restrict__ X,
                                                      const double* __restrict__ M, MlpNorm nm, int64_t n,
                                                      float* __restrict__ out) {
   __shared__ __bf16 lds[4][2][16 * SROW];
+  __shared__ float sbias[132];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-  Weights w;
-  load_weights(params, r, g, w);
+  if (threadIdx.x < 132)
+    sbias[threadIdx.x] = threadIdx.x < 64    ? params[MLP_OB1 + threadIdx.x]
+                         : threadIdx.x < 128 ? params[MLP_OB2 + threadIdx.x - 64]
+                                             : params[MLP_OB3 + threadIdx.x - 128];
+  Mats w;
+  load_mats(params, r, g, w);
+  __syncthreads();
+  const LdsBias bias{sbias, g};
   const int64_t ntiles = (n + 15) / 16;
   const int64_t stride = (int64_t)gridDim.x * 4;
-  for (int64_t base = blockIdx.x * 4ll; base < ntiles; base += stride) {
-    const int64_t tile = base + wv;
+  for (int64_t tile = blockIdx.x * 4ll + wv; tile < ntiles; tile += stride) {
     const int64_t s = tile * 16 + r;
-    const bool live = tile < ntiles && s < n;
+    const bool live = s < n;
     bf16x8 xin = zero8();
-    double rho = 1.0;
     if (g == 0 && live) {
       float f[4];
       if (WARM) {
-        rho = M[s];
+        const double rho = M[s];
         const double u1 = M[n + s] / rho, u2 = M[2 * n + s] / rho, e = M[3 * n + s] / rho;
         const double feat[4] = {u1, u2, e, u1 * u1 + u2 * u2};
         #pragma unroll
@@ -202,7 +247,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ p
       for (int k = 0; k < 4; ++k) xin[k] = (__bf16)f[k];
     }
     f32x4 y;
-    forward16<false>(w, xin, lds[wv][0], lds[wv][1], r, g, nullptr, nullptr, y);
+    forward16<false, SYNC_WAVE>(w, bias, xin, lds[wv][0], lds[wv][1], r, g, nullptr, nullptr, y);
     if (g == 0 && live) {
       if (WARM) {
         #pragma unroll
@@ -211,7 +256,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ p
         *(f32x4*)(out + s * 4) = y;
       }
     }
-    __syncthreads();  // LDS tiles are reused by the next iteration
+    tile_sync<SYNC_WAVE>();  // the wave's LDS tiles are rewritten by its next tile
   }
 }
 
@@ -326,7 +371,7 @@ __global__ __launch_bounds__(64 * GRAD_WAVES) void k_mlp_grad(const float* __res
           S.xt[k * TROW + sl] = xin[k];
         }
       }
-      forward16<true>(w, xin, S.hs1[h], S.hs2[h], r, g, z1[h], z2[h], y[h]);
+      forward16<true>(w, RegBias{w}, xin, S.hs1[h], S.hs2[h], r, g, z1[h], z2[h], y[h]);
     }
     // unit-major copies of H1 and H2 for the weight-gradient products
     #pragma unroll
