@@ -352,6 +352,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
     f.M = c->Mbuf;
     f.n = c->N;
     f.mu = c->mubuf;
+    f.prod = 1;  // the time step keeps the product-form state, not the multipliers
     f.warm = c->warm;
     f.iters = nullptr;
     f.status = nullptr;

@@ -62,11 +62,20 @@ __device__ int newton64_damped(double u1, double u2, double e, double tol, int m
   return -1;
 }
 
-__device__ __forceinline__ void write_mu(double* mu, int64_t n, int64_t i, double rho, const FS<double>& s) {
-  mu[i] = ::log(s.a * rho);
-  mu[n + i] = ::log(s.X);
-  mu[2 * n + i] = ::log(s.Y);
-  mu[3 * n + i] = ::log(s.Z);
+// the solution as multipliers mu = ln(A, X, Y, Z) or as the state itself
+__device__ __forceinline__ void write_mu(const FstarArgs& a, int64_t i, double rho, const FS<double>& s) {
+  const int64_t n = a.n;
+  if (a.prod) {
+    a.mu[i] = s.a * rho;
+    a.mu[n + i] = s.X;
+    a.mu[2 * n + i] = s.Y;
+    a.mu[3 * n + i] = s.Z;
+  } else {
+    a.mu[i] = ::log(s.a * rho);
+    a.mu[n + i] = ::log(s.X);
+    a.mu[2 * n + i] = ::log(s.Y);
+    a.mu[3 * n + i] = ::log(s.Z);
+  }
 }
 
 // Statistics are accumulated per thread over its sites, reduced per
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
       if (!feasible(rho, u1, u2, e)) {
         ninf++;
         if (__builtin_fabs(u1) < 1.0 && __builtin_fabs(u2) < 1.0 && rho > 0.0) {
-          write_mu(a.mu, n, i, rho, closed_form<double>(u1, u2));
+          write_mu(a, i, rho, closed_form<double>(u1, u2));
         } else {
           for (int c = 0; c < 4; ++c) a.mu[c * n + i] = __builtin_nan("");
         }
@@ -118,11 +127,18 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
           s.Y = __expf(a.warm[2 * n + i]);
           s.Z = __expf(a.warm[3 * n + i]);
         } else if (START == START_PREV) {
-          // the multipliers already in mu (e.g. the previous time step's)
-          s.a = __expf((float)a.mu[i]) / (float)rho;
-          s.X = __expf((float)a.mu[n + i]);
-          s.Y = __expf((float)a.mu[2 * n + i]);
-          s.Z = __expf((float)a.mu[3 * n + i]);
+          // the solution already in mu (e.g. the previous time step's)
+          if (a.prod) {
+            s.a = (float)(a.mu[i] / rho);
+            s.X = (float)a.mu[n + i];
+            s.Y = (float)a.mu[2 * n + i];
+            s.Z = (float)a.mu[3 * n + i];
+          } else {
+            s.a = __expf((float)a.mu[i]) / (float)rho;
+            s.X = __expf((float)a.mu[n + i]);
+            s.Y = __expf((float)a.mu[2 * n + i]);
+            s.Z = __expf((float)a.mu[3 * n + i]);
+          }
         } else {
           s.a = 4.0f / 9.0f;
           s.X = 1.0f;
@@ -146,13 +162,32 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
           s.Z *= __expf(sc * d[3]);
           ++it32;
         }
-        // ---- FP64 phase
+        // ---- FP64 phase.  The first step is a simplified Newton step with
+        // the FP32 Hessian H of the current point (its relative error ~1e-7
+        // times a residual ~1e-6 leaves ~1e-13); full FP64 Newton steps
+        // follow only if the residual is still above tol.
         FS<double> t{(double)s.a, (double)s.X, (double)s.Y, (double)s.Z};
         bool ok = false;
         if (__builtin_isfinite(t.a) && t.a > 0.0 && t.X > 0.0 && t.Y > 0.0 && t.Z > 0.0 &&
             __builtin_isfinite(t.X) && __builtin_isfinite(t.Y) && __builtin_isfinite(t.Z)) {
           double gd[4], Hd[10], dd[4];
-          for (;;) {
+          fsys_grad<double>(t, u1, u2, e, gd);
+          res = resid(gd);
+          if (res <= a.tol) {
+            ok = true;
+          } else if (res < 1e-4 && it64 < a.max64) {
+            float gf[4] = {(float)gd[0], (float)gd[1], (float)gd[2], (float)gd[3]}, df[4];
+            fsolve<float>(H, gf, df);
+            t.a *= exp_step((double)df[0]);
+            t.X *= exp_step((double)df[1]);
+            t.Y *= exp_step((double)df[2]);
+            t.Z *= exp_step((double)df[3]);
+            ++it64;
+            fsys_grad<double>(t, u1, u2, e, gd);
+            res = resid(gd);
+            ok = res <= a.tol;
+          }
+          for (; !ok;) {
             fsys<double>(t, u1, u2, e, gd, Hd);
             res = resid(gd);
             if (res <= a.tol) { ok = true; break; }
@@ -166,7 +201,7 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
           }
         }
         if (ok) {
-          write_mu(a.mu, n, i, rho, t);
+          write_mu(a, i, rho, t);
           if (a.status) a.status[i] = 0;
           maxres = fmax(maxres, res);
         } else {
@@ -223,7 +258,7 @@ __global__ __launch_bounds__(64) void k_fstar_fallback(FstarArgs a) {
     FS<double> s;
     double res = 0.0;
     const int it = newton64_damped(u1, u2, e, a.tol, 200, s, res);
-    write_mu(a.mu, n, i, rho, s);
+    write_mu(a, i, rho, s);
     if (a.status) a.status[i] = it >= 0 ? 1 : 3;
     atomicAdd(&a.stats->fallback, 1ull);
     if (it < 0) atomicAdd(&a.stats->failed, 1ull);

@@ -19,6 +19,8 @@ struct FstarArgs {
   const double* M;      // [4][n]
   int64_t n;
   double* mu;           // [4][n] (START_PREV: read as the start, then overwritten)
+  int prod;             // 0: mu holds the multipliers (ln A, ln X, ln Y, ln Z);
+                        // 1: the product-form state (A, X, Y, Z) itself
   const float* warm;    // [4][n]: (mu0 - ln rho, mu1, mu2, mu3) start, START_WARM only
   uint8_t* iters;       // [n] or null
   uint8_t* status;      // [n] or null: 0 ok, 1 fallback ok, 2 infeasible, 3 failed

@@ -40,6 +40,19 @@ __device__ __forceinline__ void fsys(const FS<T>& s, T u1, T u2, T e, T* g, T* H
   H[9] = a * (qx * ny + T(2) * qx * qy + nx * qy);
 }
 
+// the gradient alone (the convergence test)
+template <typename T>
+__device__ __forceinline__ void fsys_grad(const FS<T>& s, T u1, T u2, T e, T* g) {
+  const T ix = T(1) / s.X, iy = T(1) / s.Y;
+  const T qx = s.Z * (s.X + ix), px = s.Z * (s.X - ix), nx = T(1) + qx;
+  const T qy = s.Z * (s.Y + iy), py = s.Z * (s.Y - iy), ny = T(1) + qy;
+  const T a = s.a;
+  g[0] = a * nx * ny - T(1);
+  g[1] = a * px * ny - u1;
+  g[2] = a * nx * py - u2;
+  g[3] = a * (qx * ny + nx * qy) - e;
+}
+
 template <typename T> __device__ __forceinline__ T recip(T x) {
   if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);
   else return T(1) / x;
@@ -101,11 +114,9 @@ __device__ __forceinline__ FS<T> closed_form(T u1, T u2) {
 }
 
 
-// Newton polish in FP64 from multipliers mu (A = e^mu0 etc.) for moments M:
-// `iters` undamped steps, for the ranking of screened sites
-__device__ __forceinline__ FS<double> polish64(const double* mu, double rho, double u1, double u2, double e,
-                                               int iters) {
-  FS<double> s{::exp(mu[0]) / rho, ::exp(mu[1]), ::exp(mu[2]), ::exp(mu[3])};
+// Newton polish in FP64 from the product-form state s (a = A / rho) for
+// moments M: `iters` undamped steps, for the ranking of screened sites
+__device__ __forceinline__ FS<double> polish64(FS<double> s, double u1, double u2, double e, int iters) {
   double g[4], H[10], d[4];
   for (int it = 0; it < iters; ++it) {
     fsys<double>(s, u1, u2, e, g, H);

@@ -102,15 +102,11 @@ __device__ __forceinline__ void load_site(const T* __restrict__ A, const Geom& g
     f[i] = PULL ? pull_general<T, Q>(A, g, x, y, i) : A[sidx<Q>(g, x, y, i)];
 }
 
-// f*_M populations of site s from the multiplier buffer mu [4][N]
+// f*_M populations of site s from the solver's product-form state
+// (A, X, Y, Z) [4][N]
 template <typename T>
-__device__ __forceinline__ void fstar_from_mu_buf(const double* __restrict__ mu, int64_t N, int64_t s, T* fs) {
-  if constexpr (sizeof(T) == 4) {
-    fstar_pop<float>(__expf((float)mu[s]), __expf((float)mu[N + s]), __expf((float)mu[2 * N + s]),
-                     __expf((float)mu[3 * N + s]), fs);
-  } else {
-    fstar_pop<double>(::exp(mu[s]), ::exp(mu[N + s]), ::exp(mu[2 * N + s]), ::exp(mu[3 * N + s]), fs);
-  }
+__device__ __forceinline__ void fstar_from_state(const double* __restrict__ st, int64_t N, int64_t s, T* fs) {
+  fstar_pop<T>((T)st[s], (T)st[N + s], (T)st[2 * N + s], (T)st[3 * N + s], fs);
 }
 
 // block-wide exclusive offset of `flag` and one global atomic per block on
@@ -192,7 +188,7 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   if constexpr (QE == QE_POLY) qe_poly_br<Q, T>(m.rho, ux, uy, fs, pb);
   else if constexpr (QE == QE_ENTROPIC_MM) qe_entropic_mm<Q, T>(m.rho, ux, uy, fs);
   else {
-    if (fluid) fstar_from_mu_buf<T>(a.mu, g.nx * g.ny, x + y * g.nx, fs);
+    if (fluid) fstar_from_state<T>(a.mu, g.nx * g.ny, x + y * g.nx, fs);
     else {
       #pragma unroll
       for (int i = 0; i < Q; ++i) fs[i] = f[i];
@@ -285,7 +281,7 @@ __device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
   const int64_t y = site / g.nx, x = site - y * g.nx;
   T fs[Q];
   if constexpr (QE == QE_ENTROPIC_M) {
-    fstar_from_mu_buf<T>(a.mu, g.nx * g.ny, site, fs);
+    fstar_from_state<T>(a.mu, g.nx * g.ny, site, fs);
   } else {
     T f[Q];
     load_site<T, Q, PULL>(A, g, x, y, f);
@@ -336,15 +332,15 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
       const Moments<Q, double> m = moments<Q, double>(fd);
       double fs[Q];
       if constexpr (QE == QE_ENTROPIC_M) {
-        // the solver's multipliers polished to FP64 round-off for the ranking
+        // the solver's state polished to FP64 round-off for the ranking
         const int64_t N = g.nx * g.ny;
-        const double mus[4] = {a.mu[site], a.mu[N + site], a.mu[2 * N + site], a.mu[3 * N + site]};
         const double ir = 1.0 / m.rho;
         if (feasible(m.rho, m.jx * ir, m.jy * ir, m.e2 * ir)) {
-          const FS<double> p = polish64(mus, m.rho, m.jx * ir, m.jy * ir, m.e2 * ir, 3);
+          const FS<double> s0{a.mu[site] * ir, a.mu[N + site], a.mu[2 * N + site], a.mu[3 * N + site]};
+          const FS<double> p = polish64(s0, m.jx * ir, m.jy * ir, m.e2 * ir, 3);
           fstar_pop<double>(m.rho * p.a, p.X, p.Y, p.Z, fs);
         } else {
-          fstar_pop<double>(::exp(mus[0]), ::exp(mus[1]), ::exp(mus[2]), ::exp(mus[3]), fs);
+          fstar_from_state<double>(a.mu, N, site, fs);
         }
       } else {
         qe_eval<Q, QE, double>(m, fs);
@@ -806,7 +802,7 @@ __global__ __launch_bounds__(256) void k_init_M_pops(StepArgs a) {
       #pragma unroll
       for (int i = 0; i < 9; ++i) fs[i] = 0.0;
     } else {
-      fstar_pop<double>(::exp(a.mu[s]), ::exp(a.mu[N + s]), ::exp(a.mu[2 * N + s]), ::exp(a.mu[3 * N + s]), fs);
+      fstar_from_state<double>(a.mu, N, s, fs);
     }
     #pragma unroll
     for (int i = 0; i < 9; ++i) S[sidx<9>(g, x, y, i)] = (T)fs[i];
