@@ -252,17 +252,20 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
 // by the 32 bits of ~site (a larger key = larger Delta S, then lower site).
 // Keys are unique, so "the k largest keys" is one well-defined set.
 //   k_rank      FP64 Delta S of the screened sites; candidates are appended
-//               with one atomic per workgroup; a 2^15-bin histogram of the
-//               top key bits is built (in LDS per workgroup when many sites
-//               are screened); when more than k sites were screened, the
-//               last workgroup to finish finds the bin b* holding the k-th
-//               largest key and how many keys r to take from it.
-//   k_partition candidates above b* (or all of them, if there are at most k)
-//               are selected and returned to quasiequilibrium at once;
-//               candidates in b* go to a boundary list.
+//               with one atomic per workgroup; when more than k sites were
+//               screened, a 2^15-bin histogram of the top key bits is built
+//               (in LDS per workgroup when many sites are screened).
+//   k_partition with more than k candidates, each workgroup finds the bin b*
+//               holding the k-th largest key (and r, the keys to take from
+//               it) in the histogram; candidates above b* (or all of them,
+//               if there are at most k) are selected and returned to
+//               quasiequilibrium at once; candidates in b* go to a boundary
+//               list.
 //   k_refine    one workgroup: 8-bit radix passes over the boundary list find
 //               the r largest keys there, which are selected and reset; the
 //               statistics are written and the counters cleared.
+// (Kernel boundaries order these phases: a device-wide fence inside a
+// kernel would write back the L2 of every XCD.)
 __device__ __forceinline__ unsigned long long ds_bits(double d) {
   return (unsigned long long)__double_as_longlong(d);
 }
@@ -294,14 +297,11 @@ __device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
 
 constexpr int RANK_BLOCKS = 512;
 constexpr uint32_t LDS_HIST_MIN = 16384;  // screened sites above which the histogram is built in LDS
-constexpr uint32_t SEL_ALL = 0xFFFFFFFFu;  // b* value: every candidate is selected
 
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
   __shared__ uint32_t s_hist[HIST_BINS / 2];  // two 16-bit counts per word
   __shared__ uint32_t s_cnt[4], s_base, s_inv[4];
-  __shared__ int s_last;
-  uint32_t* s_scan = s_hist;  // reused after the histogram is flushed
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -310,6 +310,8 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
   // with at most k screened sites every candidate is selected: no histogram
   const bool need_hist = k > 0 && n > k;
   const bool lds = need_hist && n > LDS_HIST_MIN;
+  // only the workgroups that hold screened sites take part
+  if (blockIdx.x * 256u >= n) return;
   if (lds) {
     for (int j = tid; j < HIST_BINS / 2; j += 256) s_hist[j] = 0u;
     __syncthreads();
@@ -392,24 +394,15 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
       if (v >> 16) atomicAdd(&a.hist[2 * j + 1], v >> 16);
     }
   }
-  if (!need_hist) return;
+}
 
-  // the last workgroup to finish locates b* (the histogram is complete)
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&a.ctr[C_DONE], 1u) == gridDim.x - 1u;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const uint32_t nc = __atomic_load_n(&a.ctr[C_CAND], __ATOMIC_RELAXED);
-  if (nc <= k) {
-    if (tid == 0) { a.ctr[C_BSTAR] = SEL_ALL; a.ctr[C_R] = 0u; a.ctr[C_DONE] = 0u; }
-    return;
-  }
-  // thread t owns the 128 bins [HIST_BINS-1-128t-127, HIST_BINS-1-128t], top first
-  __syncthreads();
+// b*, the histogram bin that holds the k-th largest key, and r, the keys to
+// take from it (thread t of 256 owns the 128 bins from HIST_BINS-1-128t down)
+__device__ __forceinline__ void find_bstar(const uint32_t* __restrict__ hist, uint32_t k, uint32_t* s_scan,
+                                           uint32_t* s_bstar, uint32_t* s_r) {
+  const int tid = threadIdx.x;
   uint32_t local = 0;
-  for (int j = 0; j < 128; ++j) local += __atomic_load_n(&a.hist[HIST_BINS - 1 - 128 * tid - j], __ATOMIC_RELAXED);
+  for (int j = 0; j < 128; ++j) local += hist[HIST_BINS - 1 - 128 * tid - j];
   s_scan[tid] = local;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
@@ -423,27 +416,34 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
     uint32_t c = excl;
     for (int j = 0; j < 128; ++j) {
       const uint32_t b = HIST_BINS - 1 - 128 * tid - j;
-      const uint32_t h = __atomic_load_n(&a.hist[b], __ATOMIC_RELAXED);
-      if (c + h >= k) { a.ctr[C_BSTAR] = b; a.ctr[C_R] = k - c; break; }
+      const uint32_t h = hist[b];
+      if (c + h >= k) { *s_bstar = b; *s_r = k - c; break; }
       c += h;
     }
   }
-  if (tid == 0) a.ctr[C_DONE] = 0u;
+  __syncthreads();
 }
-
-constexpr int PART_BLOCKS = 256;
 
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
-  __shared__ uint32_t s_cnt[4], s_base;
+  __shared__ uint32_t s_cnt[4], s_base, s_bstar, s_r;
+  __shared__ uint32_t s_scan[256];
   __shared__ unsigned long long s_mx[4], s_mn[4];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t nc = a.ctr[C_CAND];
   const uint32_t n = a.ctr[C_SCREEN];
   const uint32_t k = (uint32_t)a.g.kmax;
-  if (nc == 0) return;
-  const bool all = k == 0 || n <= k || a.ctr[C_BSTAR] == SEL_ALL;
-  const uint32_t bstar = all ? 0u : a.ctr[C_BSTAR];
+  // only the workgroups that hold candidates take part
+  if (blockIdx.x * 256u >= nc) return;
+  // more than k candidates: every workgroup locates b* in the (complete)
+  // histogram itself; workgroup 0 records it for k_refine
+  const bool all = k == 0 || n <= k || nc <= k;
+  uint32_t bstar = 0;
+  if (!all) {
+    find_bstar(a.hist, k, s_scan, &s_bstar, &s_r);
+    bstar = s_bstar;
+    if (blockIdx.x == 0 && tid == 0) { a.ctr[C_BSTAR] = bstar; a.ctr[C_R] = s_r; }
+  }
   unsigned long long mx = 0ull, mn = ~0ull;
   for (uint32_t t0 = blockIdx.x * 256u; t0 < nc; t0 += gridDim.x * 256u) {
     const uint32_t t = t0 + tid;
@@ -484,16 +484,18 @@ __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
   }
 }
 
+// k_refine: the boundary refinement, the statistics and the clearing of the
+// counters for the next step, by one workgroup of 256 threads
 template <typename T, int Q, int QE, bool PULL>
-__global__ __launch_bounds__(1024) void k_refine(StepArgs a) {
+__global__ __launch_bounds__(256) void k_refine(StepArgs a) {
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_nsel, s_dig, s_rr, s_exact;
-  __shared__ unsigned long long s_mn[16];
+  __shared__ unsigned long long s_mn[4];
   const int tid = threadIdx.x;
   const uint32_t nc = a.ctr[C_CAND];
   const uint32_t n = a.ctr[C_SCREEN];
   const uint32_t k = (uint32_t)a.g.kmax;
-  const bool all = k == 0 || n <= k || nc <= k || a.ctr[C_BSTAR] == SEL_ALL;
+  const bool all = k == 0 || n <= k || nc <= k;
   const uint32_t nsel0 = a.ctr[C_NSEL0];
   const uint32_t m = a.ctr[C_NBND];
   unsigned long long mn = ~0ull;
@@ -508,9 +510,9 @@ __global__ __launch_bounds__(1024) void k_refine(StepArgs a) {
     for (int pass = 0; pass < 10; ++pass) {
       const bool inhi = pass < 6;
       const int sh = inhi ? 40 - 8 * pass : 24 - 8 * (pass - 6);
-      if (tid < 256) s_hist[tid] = 0;
+      s_hist[tid] = 0;
       __syncthreads();
-      for (uint32_t t = tid; t < m; t += 1024) {
+      for (uint32_t t = tid; t < m; t += 256) {
         const Cand c = a.bnd[t];
         const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
         const uint32_t lo = ~c.site;
@@ -538,7 +540,7 @@ __global__ __launch_bounds__(1024) void k_refine(StepArgs a) {
       if (done) break;
     }
     // keys of the bin that are >= T (T's unfixed low bits are zero)
-    for (uint32_t t = tid; t < m; t += 1024) {
+    for (uint32_t t = tid; t < m; t += 256) {
       const Cand c = a.bnd[t];
       const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
       const uint32_t lo = ~c.site;
@@ -560,7 +562,7 @@ __global__ __launch_bounds__(1024) void k_refine(StepArgs a) {
   if ((tid & 63) == 0) s_mn[tid >> 6] = mn;
   __syncthreads();
   if (tid == 0) {
-    for (int v = 0; v < 16; ++v) mn = s_mn[v] < mn ? s_mn[v] : mn;
+    for (int v = 0; v < 4; ++v) mn = s_mn[v] < mn ? s_mn[v] : mn;
     const unsigned long long pm = a.st->min_bits;
     mn = pm < mn ? pm : mn;
     const uint32_t nsel = k == 0 ? 0u : (nc < k ? nc : k);
@@ -580,11 +582,18 @@ __global__ __launch_bounds__(1024) void k_refine(StepArgs a) {
     a.ctr[C_BSTAR] = 0;
     a.ctr[C_R] = 0;
   }
-  // clear the histogram for the next step (k_rank fills it only when more
-  // than k sites were screened)
-  if (nc > 0 && k > 0 && n > k)
-    for (int j = tid; j < HIST_BINS; j += 1024) a.hist[j] = 0;
+  // clear the histogram for the next step (k_rank fills it, from the
+  // candidates only, when more than k sites were screened): the candidates'
+  // own bins when they are few, else every bin
+  if (nc > 0 && k > 0 && n > k) {
+    if (nc <= HIST_BINS)
+      for (uint32_t t = tid; t < nc; t += 256) a.hist[ds_bin(a.cand[t].ds)] = 0;
+    else
+      for (int j = tid; j < HIST_BINS; j += 256) a.hist[j] = 0;
+  }
 }
+
+constexpr int PART_BLOCKS = 256;
 
 // ---------------------------------------------------------------------------
 // initial state, population access, moments, sums, clearing
@@ -823,7 +832,7 @@ static hipError_t step_t(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEv
   if (a.g.ds_on) {
     hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_partition<T, Q, QE, PULL>), dim3(PART_BLOCKS), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -32,8 +32,7 @@ enum : int {
   C_NONFINITE = 3, // sticky: a non-finite moment sum was seen
   C_NSEL0 = 4,     // sites selected by k_partition (above the bin b*)
   C_SETBAD = 5,    // set_populations met a non-finite value
-  C_DONE = 6,      // k_rank workgroups finished (last one finds b*)
-  C_BSTAR = 7,     // histogram bin holding the k-th largest key, or SEL_ALL
+  C_BSTAR = 7,     // histogram bin holding the k-th largest key
   C_R = 8,         // keys still to take from bin b*
   C_NBND = 9,      // candidates in bin b* (boundary list)
   C_COUNT = 16
