@@ -282,9 +282,9 @@ int lbm_mlp_train(lbm_mlp* net, const float* X, const float* T, int64_t n, int32
     for (int64_t b = 0; b < nb; ++b) {
       perm.offset = (uint32_t)(b * batch);
       HIPCHK(launch_mlp_grad(net->params, X, T, batch, perm, net->partials, s));
-      HIPCHK(launch_mlp_reduce(net->partials, mlp_grad_blocks(batch), batch, net->grad, net->loss + b, s));
       net->t++;
-      HIPCHK(launch_adam(net->params, net->m, net->v, net->grad, net->t, (float)lr, 0.9f, 0.999f, 1e-8f, s));
+      HIPCHK(launch_mlp_reduce_adam(net->partials, mlp_grad_blocks(batch), batch, net->grad, net->loss + b,
+                                    net->params, net->m, net->v, net->t, (float)lr, 0.9f, 0.999f, 1e-8f, s));
     }
     if (loss_per_epoch) {
       HIPCHK(hipMemcpyAsync(lb.data(), net->loss, sizeof(float) * (size_t)nb, hipMemcpyDeviceToHost, s));

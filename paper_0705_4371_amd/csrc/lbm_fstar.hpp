@@ -72,5 +72,9 @@ hipError_t launch_mlp_reduce(const float* partials, int nblocks, int64_t n, floa
                              hipStream_t s);
 hipError_t launch_adam(float* params, float* m, float* v, const float* grad, int64_t t, float lr, float b1,
                        float b2, float eps, hipStream_t s);
+// the reduction followed at once by the Adam step (one launch per training step)
+hipError_t launch_mlp_reduce_adam(const float* partials, int nblocks, int64_t n, float* grad, float* loss,
+                                  float* params, float* m, float* v, int64_t t, float lr, float b1, float b2,
+                                  float eps, hipStream_t s);
 
 }  // namespace lbm

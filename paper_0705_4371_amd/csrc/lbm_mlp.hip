@@ -553,53 +553,92 @@ hipError_t launch_mlp_grad(const float* params, const float* X, const float* T, 
 }
 
 // fixed-order sum of the block partials: grad[p] and loss = sum / (4 n).
-// A block owns 64 parameters; its 4 thread groups sum the partials of
-// blocks b = q (mod 4) in increasing b, then the 4 group sums are added in
-// group order.
-__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ partials, int nblocks, int64_t n,
-                                                    float* __restrict__ grad, float* __restrict__ loss) {
-  __shared__ float red[4][64];
+// Adam (Kingma and Ba) with bias correction c1 = 1 - b1^t, c2 = 1 - b2^t
+struct AdamArgs {
+  int on;
+  float* p;
+  float* m;
+  float* v;
+  float c1, c2, lr, b1, b2, eps;
+};
+
+__device__ __forceinline__ void adam_update(const AdamArgs& a, int i, float gi) {
+  const float mi = a.b1 * a.m[i] + (1.f - a.b1) * gi;
+  const float vi = a.b2 * a.v[i] + (1.f - a.b2) * gi * gi;
+  a.m[i] = mi;
+  a.v[i] = vi;
+  a.p[i] -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+}
+
+static AdamArgs adam_args(float* params, float* m, float* v, int64_t t, float lr, float b1, float b2, float eps) {
+  AdamArgs a;
+  a.on = 1;
+  a.p = params;
+  a.m = m;
+  a.v = v;
+  a.c1 = (float)(1.0 - pow((double)b1, (double)t));
+  a.c2 = (float)(1.0 - pow((double)b2, (double)t));
+  a.lr = lr;
+  a.b1 = b1;
+  a.b2 = b2;
+  a.eps = eps;
+  return a;
+}
+
+// A block owns 64 parameters; its 16 thread groups sum the partials of
+// blocks b = q (mod 16) in increasing b, then the 16 group sums are added in
+// group order (a fixed order: the result does not depend on scheduling).
+// With ad.on the block applies the Adam step to its 64 parameters at once.
+__global__ __launch_bounds__(1024) void k_mlp_reduce(const float* __restrict__ partials, int nblocks, int64_t n,
+                                                     float* __restrict__ grad, float* __restrict__ loss,
+                                                     AdamArgs ad) {
+  __shared__ float red[16][64];
   const int q = threadIdx.x >> 6, j = threadIdx.x & 63;
   const int p = blockIdx.x * 64 + j;
   float s = 0.f;
   if (p <= MLP_NPARAM)
-    for (int b = q; b < nblocks; b += 4) s += partials[(int64_t)b * (MLP_NPARAM + 1) + p];
+    for (int b = q; b < nblocks; b += 16) s += partials[(int64_t)b * (MLP_NPARAM + 1) + p];
   red[q][j] = s;
   __syncthreads();
   if (q == 0 && p <= MLP_NPARAM) {
-    const float t = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
-    if (p < MLP_NPARAM) grad[p] = t;
-    else if (loss) *loss = t / (4.0f * (float)n);
+    float t = red[0][j];
+    for (int v = 1; v < 16; ++v) t += red[v][j];
+    if (p < MLP_NPARAM) {
+      grad[p] = t;
+      if (ad.on) adam_update(ad, p, t);
+    } else if (loss) {
+      *loss = t / (4.0f * (float)n);
+    }
   }
 }
 
 hipError_t launch_mlp_reduce(const float* partials, int nblocks, int64_t n, float* grad, float* loss,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 63) / 64), dim3(256), 0, s, partials, nblocks, n, grad,
-                     loss);
+  AdamArgs off{};
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 63) / 64), dim3(1024), 0, s, partials, nblocks, n, grad,
+                     loss, off);
   return hipGetLastError();
 }
 
-// Adam (Kingma and Ba) with bias correction; step t >= 1
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                                              const float* __restrict__ g, float c1, float c2, float lr, float b1,
-                                              float b2, float eps) {
+hipError_t launch_mlp_reduce_adam(const float* partials, int nblocks, int64_t n, float* grad, float* loss,
+                                  float* params, float* m, float* v, int64_t t, float lr, float b1, float b2,
+                                  float eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 63) / 64), dim3(1024), 0, s, partials, nblocks, n, grad,
+                     loss, adam_args(params, m, v, t, lr, b1, b2, eps));
+  return hipGetLastError();
+}
+
+// Adam step t >= 1 on all parameters (the separate entry point)
+__global__ __launch_bounds__(256) void k_adam(const float* __restrict__ g, AdamArgs a) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= MLP_NPARAM) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  adam_update(a, i, g[i]);
 }
 
 hipError_t launch_adam(float* params, float* m, float* v, const float* grad, int64_t t, float lr, float b1,
                        float b2, float eps, hipStream_t s) {
-  const float c1 = (float)(1.0 - pow((double)b1, (double)t));
-  const float c2 = (float)(1.0 - pow((double)b2, (double)t));
-  hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, params, m, v, grad, c1, c2, lr, b1,
-                     b2, eps);
+  hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, grad,
+                     adam_args(params, m, v, t, lr, b1, b2, eps));
   return hipGetLastError();
 }
 
