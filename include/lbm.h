@@ -63,6 +63,13 @@ enum { LBM_COLL_LBGK = 0, LBM_COLL_ELBM = 1 };
    mass-momentum closed form of Sec. 4.2; the warm-start network; the
    multipliers already held (previous time step / contents of mu) */
 enum { LBM_START_DEFAULT = 0, LBM_START_CLOSED_FORM = 1, LBM_START_MLP = 2, LBM_START_PREV = 3 };
+/* how the ranking and selection of a step are launched (the result is the
+   same): MANY (and AUTO) spread them over many workgroups in three kernels,
+   whose cost grows gently with the number of sites above delta; ONE runs
+   them in a single workgroup in one kernel, about 3 us per step cheaper on
+   a healthy lattice of ~10^5-10^6 sites but slow when many sites are above
+   delta (an outbreak: ~0.3 ms per step at 5 x 10^5 screened sites) */
+enum { LBM_SELECT_AUTO = 0, LBM_SELECT_ONE = 1, LBM_SELECT_MANY = 2 };
 
 typedef struct lbm_ctx lbm_ctx; /* opaque; owns all device memory it allocates */
 typedef struct lbm_mlp lbm_mlp; /* opaque; owns weights and optimiser state    */
@@ -80,6 +87,8 @@ typedef struct lbm_config {
                          per-site Newton solve in every step; the residual
                          target is 1e-10 (FP32 contexts) or 1e-13 (FP64)      */
   int32_t bc[4];      /* west, east, south, north                               */
+  int32_t select_mode;/* LBM_SELECT_*                                           */
+  int32_t reserved;   /* 0                                                      */
   double inlet_rho;   /* inlet state for LBM_BC_INLET_EQ                        */
   double inlet_u[2];
   int64_t solid_x0, solid_y0, solid_w, solid_h; /* solid square (w == 0: none)  */

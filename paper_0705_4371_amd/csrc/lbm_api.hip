@@ -152,6 +152,8 @@ int lbm_validate_config(const lbm_config* c) {
   if (!(c->nu >= 0.0)) return fail(LBM_E_INVAL, "nu must be >= 0 (got %g)", c->nu);
   if (!(c->delta >= 0.0)) return fail(LBM_E_INVAL, "delta must be >= 0 or +inf (got %g)", c->delta);
   if (c->k < 0) return fail(LBM_E_INVAL, "k must be >= 0 (got %d)", c->k);
+  if (c->select_mode != LBM_SELECT_AUTO && c->select_mode != LBM_SELECT_ONE && c->select_mode != LBM_SELECT_MANY)
+    return fail(LBM_E_INVAL, "select_mode must be one of LBM_SELECT_* (got %d)", c->select_mode);
   for (int s = 0; s < 4; ++s) {
     const int b = c->bc[s];
     const bool ok = s < 2 ? (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_INLET_EQ ||
@@ -319,6 +321,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   a.qe = cfg->qe;
   a.probe = -1;
   a.probe_cap = 1;
+  a.one_wg = cfg->select_mode == LBM_SELECT_ONE;
 
   const size_t bytes = (size_t)Q * (size_t)c->plane * c->elem;
   const size_t ncap = (size_t)c->N;

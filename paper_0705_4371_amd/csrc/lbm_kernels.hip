@@ -295,6 +295,36 @@ __device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
   for (int i = 0; i < Q; ++i) B[sidx<Q>(g, x, y, i)] = fs[i];
 }
 
+// FP64 Delta S of one site for the ranking: f(x, t) re-pulled from the
+// state, promoted to FP64; f* in FP64 (for f*_M the solver's state polished
+// to FP64 round-off)
+template <typename T, int Q, int QE, bool PULL>
+__device__ __forceinline__ double rank_site(const StepArgs& a, const T* __restrict__ A, const Geom& g,
+                                            uint32_t site) {
+  const int64_t y = site / g.nx, x = site - y * g.nx;
+  T fT[Q];
+  load_site<T, Q, PULL>(A, g, x, y, fT);
+  double fd[Q];
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) fd[i] = (double)fT[i];
+  const Moments<Q, double> m = moments<Q, double>(fd);
+  double fs[Q];
+  if constexpr (QE == QE_ENTROPIC_M) {
+    const int64_t N = g.nx * g.ny;
+    const double ir = 1.0 / m.rho;
+    if (feasible(m.rho, m.jx * ir, m.jy * ir, m.e2 * ir)) {
+      const FS<double> s0{a.mu[site] * ir, a.mu[N + site], a.mu[2 * N + site], a.mu[3 * N + site]};
+      const FS<double> p = polish64(s0, m.jx * ir, m.jy * ir, m.e2 * ir, 3);
+      fstar_pop<double>(m.rho * p.a, p.X, p.Y, p.Z, fs);
+    } else {
+      fstar_from_state<double>(a.mu, N, site, fs);
+    }
+  } else {
+    qe_eval<Q, QE, double>(m, fs);
+  }
+  return dS_fp64<Q>(fd, fs);
+}
+
 constexpr int RANK_BLOCKS = 512;
 constexpr uint32_t LDS_HIST_MIN = 16384;  // screened sites above which the histogram is built in LDS
 
@@ -325,29 +355,7 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
     uint32_t site = 0;
     if (t < n) {
       site = a.screen[t];
-      const int64_t y = site / g.nx, x = site - y * g.nx;
-      T fT[Q];
-      load_site<T, Q, PULL>(A, g, x, y, fT);
-      double fd[Q];
-      #pragma unroll
-      for (int i = 0; i < Q; ++i) fd[i] = (double)fT[i];
-      const Moments<Q, double> m = moments<Q, double>(fd);
-      double fs[Q];
-      if constexpr (QE == QE_ENTROPIC_M) {
-        // the solver's state polished to FP64 round-off for the ranking
-        const int64_t N = g.nx * g.ny;
-        const double ir = 1.0 / m.rho;
-        if (feasible(m.rho, m.jx * ir, m.jy * ir, m.e2 * ir)) {
-          const FS<double> s0{a.mu[site] * ir, a.mu[N + site], a.mu[2 * N + site], a.mu[3 * N + site]};
-          const FS<double> p = polish64(s0, m.jx * ir, m.jy * ir, m.e2 * ir, 3);
-          fstar_pop<double>(m.rho * p.a, p.X, p.Y, p.Z, fs);
-        } else {
-          fstar_from_state<double>(a.mu, N, site, fs);
-        }
-      } else {
-        qe_eval<Q, QE, double>(m, fs);
-      }
-      ds = dS_fp64<Q>(fd, fs);
+      ds = rank_site<T, Q, QE, PULL>(a, A, g, site);
       is_c = ds > g.delta;
     }
     const uint32_t slot = block_append(is_c, &a.ctr[C_CAND], s_cnt, &s_base);
@@ -596,6 +604,199 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
 constexpr int PART_BLOCKS = 256;
 
 // ---------------------------------------------------------------------------
+// k_select_one: the whole ranking and selection in one workgroup of 512
+// threads (LBM_SELECT_ONE), for small healthy lattices, where each kernel
+// boundary costs as much as the work: the same candidates, keys and selected
+// set as k_rank + k_partition + k_refine, in one launch instead of three.  The histogram
+// lives in LDS (2^15 32-bit counts), the counters in LDS.
+// ---------------------------------------------------------------------------
+constexpr int ONE_TX = 512;
+constexpr int ONE_BINS = HIST_BINS / ONE_TX;  // histogram bins owned by a thread in the b* scan
+
+// workgroup-wide exclusive offset of `flag` over the ONE_TX / 64 waves, base
+// from an LDS counter *s_total (no global atomic); s_cnt: ONE_TX / 64 words
+__device__ __forceinline__ uint32_t append_one(bool flag, uint32_t* s_total, uint32_t* s_cnt) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const unsigned long long mask = __ballot(flag);
+  if (lane == 0) s_cnt[w] = (uint32_t)__popcll(mask);
+  __syncthreads();
+  uint32_t base = *s_total;
+  for (int v = 0; v < w; ++v) base += s_cnt[v];
+  const uint32_t slot = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (tid == ONE_TX - 1) {
+    uint32_t tot = 0;
+    for (int v = 0; v < ONE_TX / 64; ++v) tot += s_cnt[v];
+    *s_total += tot;
+  }
+  __syncthreads();
+  return slot;
+}
+
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(ONE_TX) void k_select_one(StepArgs a) {
+  __shared__ uint32_t s_hist[HIST_BINS];
+  __shared__ uint32_t s_cnt[ONE_TX / 64];
+  __shared__ uint32_t s_nc, s_ninv, s_nsel, s_nbnd, s_bstar, s_r, s_dig, s_rr, s_exact;
+  __shared__ uint32_t s_scan[ONE_TX];
+  __shared__ unsigned long long s_mx[ONE_TX / 64], s_mn[ONE_TX / 64];
+  const T* __restrict__ A = (const T*)a.A;
+  const Geom& g = a.g;
+  const int tid = threadIdx.x;
+  const uint32_t n = a.ctr[C_SCREEN];
+  const uint32_t k = (uint32_t)g.kmax;
+  const bool need_hist = k > 0 && n > k;
+  if (tid == 0) { s_nc = 0; s_ninv = 0; s_nsel = 0; s_nbnd = 0; s_bstar = 0; s_r = 0; }
+  if (need_hist)
+    for (int j = tid; j < HIST_BINS; j += ONE_TX) s_hist[j] = 0u;
+  __syncthreads();
+  // 1. FP64 Delta S of the screened sites (as in k_rank)
+  for (uint32_t t0 = 0; t0 < n; t0 += ONE_TX) {
+    const uint32_t t = t0 + tid;
+    bool is_c = false;
+    double ds = 0.0;
+    uint32_t site = 0;
+    if (t < n) {
+      site = a.screen[t];
+      ds = rank_site<T, Q, QE, PULL>(a, A, g, site);
+      is_c = ds > g.delta;
+    }
+    const uint32_t slot = append_one(is_c, &s_nc, s_cnt);
+    if (is_c) {
+      a.cand[slot] = Cand{site, 0u, ds};
+      if (need_hist) atomicAdd(&s_hist[ds_bin(ds)], 1u);
+      if (__builtin_isinf(ds)) atomicAdd(&s_ninv, 1u);
+    }
+  }
+  __syncthreads();
+  const uint32_t nc = s_nc;
+  const bool all = k == 0 || nc <= k;
+  // 2. b* from the histogram (thread t owns the ONE_BINS bins from
+  //    HIST_BINS-1-ONE_BINS t down)
+  if (!all) {
+    uint32_t local = 0;
+    for (int j = 0; j < ONE_BINS; ++j) local += s_hist[HIST_BINS - 1 - ONE_BINS * tid - j];
+    s_scan[tid] = local;
+    __syncthreads();
+    for (int off = 1; off < ONE_TX; off <<= 1) {
+      const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
+      __syncthreads();
+      s_scan[tid] += v;
+      __syncthreads();
+    }
+    const uint32_t incl = s_scan[tid], excl = incl - local;
+    if (excl < k && incl >= k) {
+      uint32_t c = excl;
+      for (int j = 0; j < ONE_BINS; ++j) {
+        const uint32_t b = HIST_BINS - 1 - ONE_BINS * tid - j;
+        const uint32_t h = s_hist[b];
+        if (c + h >= k) { s_bstar = b; s_r = k - c; break; }
+        c += h;
+      }
+    }
+    __syncthreads();
+  }
+  const uint32_t bstar = s_bstar;
+  // 3. keys above b* (or all) are selected and reset; keys in b* listed
+  unsigned long long mx = 0ull, mn = ~0ull;
+  for (uint32_t t0 = 0; t0 < nc; t0 += ONE_TX) {
+    const uint32_t t = t0 + tid;
+    Cand c{0u, 0u, 0.0};
+    if (t < nc) c = a.cand[t];
+    const uint32_t bin = ds_bin(c.ds);
+    const bool take = t < nc && k > 0 && (all || bin > bstar);
+    const bool bnd = t < nc && !all && bin == bstar;
+    if (t < nc) mx = ds_bits(c.ds) > mx ? ds_bits(c.ds) : mx;
+    if (take) mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
+    const uint32_t s1 = append_one(take, &s_nsel, s_cnt);
+    const uint32_t s2 = append_one(bnd, &s_nbnd, s_cnt);
+    if (take) {
+      a.sel[s1] = c.site;
+      a.sel_ds[s1] = c.ds;
+      reset_site<T, Q, QE, PULL>(a, c.site);
+    }
+    if (bnd) a.bnd[s2] = c;
+  }
+  __syncthreads();
+  // 4. the r largest keys of bin b*: 8-bit radix passes (as in k_refine)
+  if (!all) {
+    const uint32_t m = s_nbnd;
+    unsigned long long Thi = 0, Mhi = 0;
+    uint32_t Tlo = 0, Mlo = 0, rr = s_r;
+    uint32_t* s_h8 = s_scan;  // 256 digit counts
+    for (int pass = 0; pass < 10; ++pass) {
+      const bool inhi = pass < 6;
+      const int sh = inhi ? 40 - 8 * pass : 24 - 8 * (pass - 6);
+      if (tid < 256) s_h8[tid] = 0;
+      __syncthreads();
+      for (uint32_t t = tid; t < m; t += ONE_TX) {
+        const Cand c = a.bnd[t];
+        const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
+        const uint32_t lo = ~c.site;
+        if ((hi & Mhi) == Thi && (lo & Mlo) == Tlo) {
+          const uint32_t d = inhi ? (uint32_t)(hi >> sh) & 255u : (lo >> sh) & 255u;
+          atomicAdd(&s_h8[d], 1u);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t c = 0;
+        for (int d = 255; d >= 0; --d) {
+          const uint32_t h = s_h8[d];
+          if (c + h >= rr) { s_dig = (uint32_t)d; s_rr = rr - c; s_exact = (h == rr - c); break; }
+          c += h;
+        }
+      }
+      __syncthreads();
+      const uint32_t d = s_dig;
+      rr = s_rr;
+      if (inhi) { Thi |= (unsigned long long)d << sh; Mhi |= 255ull << sh; }
+      else { Tlo |= d << sh; Mlo |= 255u << sh; }
+      const bool done = s_exact != 0;
+      __syncthreads();
+      if (done) break;
+    }
+    for (uint32_t t = tid; t < m; t += ONE_TX) {
+      const Cand c = a.bnd[t];
+      const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
+      const uint32_t lo = ~c.site;
+      if (hi > Thi || (hi == Thi && lo >= Tlo)) {
+        const uint32_t i = atomicAdd(&s_nsel, 1u);  // s_nsel starts at nsel0
+        if (i < k) {
+          a.sel[i] = c.site;
+          a.sel_ds[i] = c.ds;
+          reset_site<T, Q, QE, PULL>(a, c.site);
+        }
+        mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
+      }
+    }
+  }
+  // 5. statistics; counters cleared for the next step
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long ox = (unsigned long long)__shfl_xor((long long)mx, off);
+    const unsigned long long on = (unsigned long long)__shfl_xor((long long)mn, off);
+    mx = ox > mx ? ox : mx;
+    mn = on < mn ? on : mn;
+  }
+  if ((tid & 63) == 0) { s_mx[tid >> 6] = mx; s_mn[tid >> 6] = mn; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int v = 0; v < ONE_TX / 64; ++v) {
+      mx = s_mx[v] > mx ? s_mx[v] : mx;
+      mn = s_mn[v] < mn ? s_mn[v] : mn;
+    }
+    const uint32_t nsel = k == 0 ? 0u : (nc < k ? nc : k);
+    a.st->n_above = nc;
+    a.st->n_sel = nsel;
+    a.st->n_invalid = s_ninv;
+    a.st->total_sel += nsel;
+    a.st->max = nc ? __longlong_as_double((long long)mx) : 0.0;
+    a.st->kth = nsel ? __longlong_as_double((long long)mn) : 0.0;
+    a.ctr[C_SCREEN] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // initial state, population access, moments, sums, clearing
 // ---------------------------------------------------------------------------
 template <typename T, int Q, int QE>
@@ -829,7 +1030,9 @@ static hipError_t step_t(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEv
   else
     hipLaunchKernelGGL((k_step<T, Q, QE, PULL>), dim3((unsigned)a.nblocks), dim3(STEP_TX), 0, s, a);
   if (ev1) { hipError_t e = hipEventRecord(ev1, s); if (e != hipSuccess) return e; }
-  if (a.g.ds_on) {
+  if (a.g.ds_on && a.one_wg) {
+    hipLaunchKernelGGL((k_select_one<T, Q, QE, PULL>), dim3(1), dim3(ONE_TX), 0, s, a);
+  } else if (a.g.ds_on) {
     hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_partition<T, Q, QE, PULL>), dim3(PART_BLOCKS), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(256), 0, s, a);

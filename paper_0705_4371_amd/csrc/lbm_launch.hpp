@@ -61,6 +61,7 @@ struct StepArgs {
   int64_t ntx, nblocks;
   int prec, Q, qe;
   int coll;  // 0 LBGK, 1 ELBM
+  int one_wg;  // ranking and selection by one workgroup (k_select_one)
   // monitoring point: site index (-1: none), ring [3][probe_cap] of
   // (rho, u1, u2) of f(x, t), and the device count of recorded samples
   int64_t probe;

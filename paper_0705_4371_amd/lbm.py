@@ -24,6 +24,7 @@ LBM_FP32, LBM_FP64 = 0, 1
 LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ, LBM_BC_OUTLET_EQ = 0, 1, 2, 3, 4
 LBM_COLL_LBGK, LBM_COLL_ELBM = 0, 1
 LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP, LBM_START_PREV = 0, 1, 2, 3
+LBM_SELECT_AUTO, LBM_SELECT_ONE, LBM_SELECT_MANY = 0, 1, 2
 
 
 class lbm_config(C.Structure):
@@ -32,7 +33,7 @@ class lbm_config(C.Structure):
         ("nx", C.c_int64), ("ny", C.c_int64),
         ("nu", C.c_double), ("delta", C.c_double),
         ("k", C.c_int32), ("fstar_start", C.c_int32),
-        ("bc", C.c_int32 * 4),
+        ("bc", C.c_int32 * 4), ("select_mode", C.c_int32), ("reserved", C.c_int32),
         ("inlet_rho", C.c_double), ("inlet_u", C.c_double * 2),
         ("solid_x0", C.c_int64), ("solid_y0", C.c_int64), ("solid_w", C.c_int64), ("solid_h", C.c_int64),
         ("net", C.c_void_p), ("stream", C.c_void_p),
@@ -135,7 +136,7 @@ def check(code: int, where: str) -> None:
 def make_config(lattice=LBM_D2Q9, qe=LBM_QE_POLY, precision=LBM_FP32, nx=64, ny=64, nu=1e-3,
                 delta=math.inf, k=0, bc=(LBM_BC_PERIODIC,) * 4, inlet_rho=1.0, inlet_u=(0.0, 0.0),
                 solid=(0, 0, 0, 0), collision=LBM_COLL_LBGK, fstar_start=LBM_START_DEFAULT,
-                stream=None) -> lbm_config:
+                select_mode=0, stream=None) -> lbm_config:
     c = lbm_config()
     load().lbm_config_default(C.byref(c))
     c.lattice, c.qe, c.precision, c.collision = lattice, qe, precision, collision
@@ -146,19 +147,20 @@ def make_config(lattice=LBM_D2Q9, qe=LBM_QE_POLY, precision=LBM_FP32, nx=64, ny=
     c.inlet_u[0], c.inlet_u[1] = inlet_u
     c.solid_x0, c.solid_y0, c.solid_w, c.solid_h = solid
     c.fstar_start = fstar_start
+    c.select_mode = select_mode
     c.stream = stream
     return c
 
 
 def config_from_workload(d: dict, precision: int, stream=None, fstar_start=LBM_START_DEFAULT,
-                         net=None) -> lbm_config:
+                         net=None, select_mode=0) -> lbm_config:
     """Config from a workloads.* parameter dict (keys Q, qe, nx, ny, nu, ...)."""
     c = make_config(lattice=d["Q"], qe=d.get("qe", LBM_QE_POLY), precision=precision,
                     nx=d["nx"], ny=d["ny"], nu=d["nu"], delta=d.get("delta", math.inf),
                     k=d.get("k", 0), bc=d.get("bc", (LBM_BC_PERIODIC,) * 4),
                     inlet_rho=d.get("inlet_rho", 1.0), inlet_u=d.get("inlet_u", (0.0, 0.0)),
                     solid=d.get("solid", (0, 0, 0, 0)), fstar_start=fstar_start,
-                    collision=d.get("collision", LBM_COLL_LBGK), stream=stream)
+                    collision=d.get("collision", LBM_COLL_LBGK), select_mode=select_mode, stream=stream)
     if net is not None:
         c.net = net.h
     return c
@@ -299,7 +301,9 @@ def strouhal(d: dict, rho0, u0, meta: dict, precision: int = LBM_FP32, steps=Non
     (checked every `chunk` steps; progress(step, t_max, stats) is called then)."""
     t_max = int(steps if steps is not None else meta["t_max"])
     n = max(2, int(round(meta["window"] * t_max)))
-    lat = Lattice(config_from_workload(d, precision), rho0, u0)
+    # one-workgroup selection: a healthy run has few sites above delta, and
+    # the run stops at the first chunk with non-finite populations
+    lat = Lattice(config_from_workload(d, precision, select_mode=LBM_SELECT_ONE), rho0, u0)
     try:
         lat.set_probe(meta["probe"][0], meta["probe"][1], n)
         done, finite = 0, True

@@ -21,9 +21,10 @@ def torch_gpu():
     return torch
 
 
-def lattice(d, precision, rho, u, stream=None, twoE0=None, fstar_start=0, net=None):
+def lattice(d, precision, rho, u, stream=None, twoE0=None, fstar_start=0, net=None, select_mode=0):
     import paper_0705_4371_amd.lbm as lbm
-    cfg = lbm.config_from_workload(d, precision, stream=stream, fstar_start=fstar_start, net=net)
+    cfg = lbm.config_from_workload(d, precision, stream=stream, fstar_start=fstar_start, net=net,
+                                   select_mode=select_mode)
     return lbm.Lattice(cfg, rho, u, twoE0)
 
 

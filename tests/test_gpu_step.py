@@ -269,3 +269,43 @@ def test_elbm_d2q9(prec):
     d, rho, u = W.shear_layer(nx=140, ny=30, k=9, delta=1e-5, width=8.0)
     d = dict(d, qe=W.QE_ENTROPIC_MM, collision=1)
     _run(d, rho, u, prec, 18, 0.03, label="elbm d2q9")
+
+
+SELECT_CASES = {
+    "ties, n >> k": lambda: W.shear_layer(nx=200, ny=40, k=37, delta=1e-6, width=5.0),
+    "delta 0": lambda: W.shear_layer(nx=130, ny=20, k=64, delta=0.0, width=5.0),
+    "n < k": lambda: W.shear_layer(nx=96, ny=16, k=5000, delta=1e-5, width=5.0),
+    "k 0": lambda: W.shear_layer(nx=96, ny=16, k=0, delta=1e-5, width=5.0),
+    "cylinder": lambda: W.cylinder(nx=240, ny=80, side=16, centre=(60, 40), re=5000.0, k=9, delta=1e-5),
+}
+
+
+@pytest.mark.parametrize("name", list(SELECT_CASES))
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_select_paths_agree(name, prec):
+    """The one-workgroup and the multi-workgroup ranking and selection give
+    bit-identical populations, selected sets and statistics (and both match
+    the oracle)."""
+    torch = torch_gpu()
+    d, rho, u = SELECT_CASES[name]()
+    say("case select paths", name, "prec", prec)
+    runs = []
+    for mode in (1, 2):
+        lat = lattice(d, prec, rho, u, select_mode=mode)
+        f = perturb(lat.get_populations().double().cpu().numpy(), 71, 0.01, d.get("solid"))
+        if name == "ties, n >> k":
+            f[:, 3:31, 17] = f[:, 2:3, 17]
+        lat.set_populations(torch.from_numpy(f))
+        f = lat.get_populations().double().cpu().numpy()
+        res = []
+        for s in range(2):
+            g, o, st = compare_step(lat, d, f, TOL[prec], label="%s mode %d step %d" % (name, mode, s))
+            _, sel, sel_ds = lat.stats(sel_cap=max(d["k"], 1))
+            res.append((g, sel, sel_ds, st.n_above_delta, st.n_selected, st.n_invalid, st.kth_dS, st.max_dS))
+            f = g
+        runs.append(res)
+        lat.close()
+    for (a, b) in zip(runs[0], runs[1]):
+        assert np.array_equal(a[0], b[0])
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        assert a[3:] == b[3:]
