@@ -73,6 +73,7 @@ def _bad(L, **kw):
     (dict(collision=4, qe=1), "collision"),
     (dict(qe=2, lattice=3, ny=1), "D2Q9"),
     (dict(bc=(0, 0, 4, 4)), "not allowed"),
+    (dict(select_mode=3), "select_mode"),
     (dict(nx=2, ny=4, bc=(3, 4, 2, 2)), "nx >= 3"),
     (dict(nx=100, ny=50, bc=(3, 4, 2, 2), solid=(60, 20, 39, 5)), "clear of an outlet"),
     (dict(nx=100, ny=50, bc=(4, 3, 2, 2), solid=(1, 20, 10, 5)), "clear of an outlet"),
