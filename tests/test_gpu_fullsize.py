@@ -4,7 +4,8 @@ one step at sampled output sites (oracle.step_sites) given the selected set,
 and Delta S at every GPU candidate and at sampled other sites.
 
 Bars as in test_gpu_step.py: FP32 populations within 1e-5 of the oracle
-(relative to max |f|), candidate Delta S within 1e-12 of max(Delta S, delta),
+(relative to max |f|), FP64 within 1e-12, candidate Delta S within 1e-12 of
+max(Delta S, delta),
 no false negatives among sampled sites, the selected set equal to the top k
 of the candidates by (oracle Delta S desc, site asc) except at sites within
 1e-12 of the k-th value.
@@ -42,7 +43,7 @@ def _check_selection(oc, d, f, sites, ds, sel):
     return set(sel.tolist())
 
 
-def _sampled_step(lat, d, f, rng, extra_sites=(), nsample=3000):
+def _sampled_step(lat, d, f, rng, extra_sites=(), nsample=3000, tol=1e-5):
     """One GPU step from f (the GPU's canonical state), checked at sampled sites."""
     oc = oracle.cfg_from_dict(d)
     lat.step(1)
@@ -69,7 +70,7 @@ def _sampled_step(lat, d, f, rng, extra_sites=(), nsample=3000):
     got = g.reshape(d["Q"], -1)[:, out_sites].double().cpu().numpy().T
     err = np.abs(got - want).max() / np.abs(want).max()
     say("  sampled %d sites, candidates %d, selected %d, rel err %.3g" % (out_sites.size, sites.size, sel.size, err))
-    assert err <= 1e-5
+    assert err <= tol
     return g.double().cpu().numpy(), st
 
 
@@ -139,4 +140,48 @@ def test_cylinder_fstarM_full_size():
     g, st = _sampled_step(lat, d, f, r, extra, nsample=1500)
     assert st.n_selected == min(d["k"], st.n_above_delta) and st.n_above_delta > 0
     assert st.n_fallback == 0
+    lat.close()
+
+
+def test_shear_layer_full_size_fp64():
+    """The FP64 context at the full size (2.4 GB per population buffer)."""
+    torch = torch_gpu()
+    say("full-size shear layer 8192 x 4096 FP64")
+    d, rho, u = W.shear_layer()
+    lat = lattice(d, 1, rho, u)
+    del rho, u
+    f = lat.get_populations()
+    r = np.random.default_rng(3)
+    band = torch.from_numpy(1 + 0.05 * r.uniform(-1, 1, (9, 12, d["nx"]))).cuda()
+    f[:, 3000:3012, :] *= band
+    lat.set_populations(f)
+    del f
+    f = lat.get_populations().cpu().numpy()
+    nx = d["nx"]
+    extra = np.concatenate([3000 * nx + np.arange(0, nx, 31), 3011 * nx + np.arange(7, nx, 43)])
+    g, st = _sampled_step(lat, d, f, r, extra, tol=1e-12)
+    assert st.n_above_delta > 4 * d["k"] and st.n_selected == d["k"]
+    lat.close()
+
+
+def test_cylinder_elbm_full_size():
+    """ELBM (alpha by bisection at every site) with the entropic
+    mass-momentum QE on the 1200 x 400 cylinder."""
+    torch = torch_gpu()
+    say("full-size ELBM cylinder 1200 x 400 FP32")
+    d, rho, u = W.cylinder(re=20000.0, qe=W.QE_ENTROPIC_MM)
+    d = dict(d, collision=1)
+    lat = lattice(d, FP32, rho, u)
+    f = lat.get_populations()
+    r = np.random.default_rng(4)
+    x0, y0, w, h = d["solid"]
+    pert = torch.from_numpy(1 + 0.1 * r.uniform(-1, 1, (9, h + 40, w + 80))).float().cuda()
+    f[:, y0 - 20:y0 + h + 20, x0 - 20:x0 + w + 60] *= pert
+    f[:, y0:y0 + h, x0:x0 + w] = 0
+    lat.set_populations(f)
+    f = lat.get_populations().double().cpu().numpy()
+    nx, ny = d["nx"], d["ny"]
+    ring = [(y * nx + x) for y in range(y0 - 2, y0 + h + 2) for x in range(x0 - 2, x0 + w + 2)]
+    g, st = _sampled_step(lat, d, f, r, np.array(ring), nsample=1500)
+    assert st.n_selected == min(d["k"], st.n_above_delta) and st.n_above_delta > 0
     lat.close()
