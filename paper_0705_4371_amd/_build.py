@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 
 SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_fstar.hip", "lbm_mlp.hip", "lbm_api_learn.hip",
            "lbm_spectrum.hip"]
-HEADERS = ["lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_internal.hpp"]
+HEADERS = ["lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_internal.hpp",
+           "lbm_fstar_site.hpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions are generated
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -253,10 +253,15 @@ static hipError_t step_once(const lbm_ctx* c, int src, int dst, bool pull, hipSt
                             hipEvent_t e1) {
   const StepArgs a = args_for(c, src, dst);
   if (c->cfg.qe == LBM_QE_ENTROPIC_M) {
-    hipError_t e = launch_moments_M(a, pull, s);
-    if (e == hipSuccess && c->fkind == START_WARM)
-      e = launch_mlp_warm(c->cfg.net->params, c->cfg.net->norm, c->Mbuf, c->N, c->warm, s);
-    if (e == hipSuccess) e = launch_fstar(c->fa, c->fkind, s);
+    hipError_t e;
+    if (c->fkind == START_WARM) {
+      // the network needs the moments of every site in memory
+      e = launch_moments_M(a, pull, s);
+      if (e == hipSuccess) e = launch_mlp_warm(c->cfg.net->params, c->cfg.net->norm, c->Mbuf, c->N, c->warm, s);
+      if (e == hipSuccess) e = launch_fstar(c->fa, c->fkind, s);
+    } else {
+      e = launch_fstar_lattice(a, c->fa, c->fkind, pull, s);
+    }
     if (e != hipSuccess) return e;
   }
   return launch_step(a, pull, s, e0, e1);

@@ -19,6 +19,7 @@
 
 #include "lbm_fstar.hpp"
 #include "lbm_fstar_dev.hpp"
+#include "lbm_fstar_site.hpp"
 
 namespace lbm {
 
@@ -62,44 +63,16 @@ __device__ int newton64_damped(double u1, double u2, double e, double tol, int m
   return -1;
 }
 
-// the solution as multipliers mu = ln(A, X, Y, Z) or as the state itself
-__device__ __forceinline__ void write_mu(const FstarArgs& a, int64_t i, double rho, const FS<double>& s) {
-  const int64_t n = a.n;
-  if (a.prod) {
-    a.mu[i] = s.a * rho;
-    a.mu[n + i] = s.X;
-    a.mu[2 * n + i] = s.Y;
-    a.mu[3 * n + i] = s.Z;
-  } else {
-    a.mu[i] = ::log(s.a * rho);
-    a.mu[n + i] = ::log(s.X);
-    a.mu[2 * n + i] = ::log(s.Y);
-    a.mu[3 * n + i] = ::log(s.Z);
-  }
-}
-
-// Statistics are accumulated per thread over its sites, reduced per
-// wavefront with shuffles and per block in LDS, and added to the global
-// counters once per block (the grid is capped so that these atomics stay few).
-struct SolveAcc {
-  uint32_t hist[16];
-  uint32_t sum32, sum64, infeasible, pad;
-  unsigned long long maxres_bits;
-};
-
-constexpr int FSTAR_MAX_BLOCKS = 2048;
-
 template <int START>
 __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
   __shared__ SolveAcc sh;
   if (threadIdx.x < sizeof(SolveAcc) / 4) ((uint32_t*)&sh)[threadIdx.x] = 0;
   __syncthreads();
   const int64_t n = a.n;
-  const int lane = threadIdx.x & 63;
   uint32_t sum32 = 0, sum64 = 0, ninf = 0;
   double maxres = 0.0;
   // the trip count is uniform across the block so that every lane takes part
-  // in the wavefront-level histogram below
+  // in the wavefront-level histogram
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t base = blockIdx.x * 256ll; base < n; base += stride) {
     const int64_t i = base + threadIdx.x;
@@ -107,145 +80,19 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
     int it32 = 0, it64 = 0;
     if (live) {
       const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
-      double res = 0.0;
-      if (!feasible(rho, u1, u2, e)) {
-        ninf++;
-        if (__builtin_fabs(u1) < 1.0 && __builtin_fabs(u2) < 1.0 && rho > 0.0) {
-          write_mu(a, i, rho, closed_form<double>(u1, u2));
-        } else {
-          for (int c = 0; c < 4; ++c) a.mu[c * n + i] = __builtin_nan("");
-        }
-        if (a.status) a.status[i] = 2;
-      } else {
-        // ---- FP32 phase
-        FS<float> s;
-        if (START == START_CLOSED) {
-          s = closed_form<float>((float)u1, (float)u2);
-        } else if (START == START_WARM) {
-          s.a = __expf(a.warm[i]);
-          s.X = __expf(a.warm[n + i]);
-          s.Y = __expf(a.warm[2 * n + i]);
-          s.Z = __expf(a.warm[3 * n + i]);
-        } else if (START == START_PREV) {
-          // the solution already in mu (e.g. the previous time step's)
-          if (a.prod) {
-            s.a = (float)(a.mu[i] / rho);
-            s.X = (float)a.mu[n + i];
-            s.Y = (float)a.mu[2 * n + i];
-            s.Z = (float)a.mu[3 * n + i];
-          } else {
-            s.a = __expf((float)a.mu[i]) / (float)rho;
-            s.X = __expf((float)a.mu[n + i]);
-            s.Y = __expf((float)a.mu[2 * n + i]);
-            s.Z = __expf((float)a.mu[3 * n + i]);
-          }
-        } else {
-          s.a = 4.0f / 9.0f;
-          s.X = 1.0f;
-          s.Y = 1.0f;
-          s.Z = 0.25f;
-        }
-        const float fu1 = (float)u1, fu2 = (float)u2, fe = (float)e;
-        float g[4], H[10], d[4];
-        float prev = 3.0e38f;
-        for (;;) {
-          fsys<float>(s, fu1, fu2, fe, g, H);
-          const float r = resid(g);
-          if (!(r > a.tol32) || it32 >= a.max32 || !(r < 0.25f * prev)) break;
-          prev = r;
-          fsolve<float>(H, g, d);
-          float dm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
-          const float sc = dm > 1.0f ? 1.0f / dm : 1.0f;
-          s.a *= __expf(sc * d[0]);
-          s.X *= __expf(sc * d[1]);
-          s.Y *= __expf(sc * d[2]);
-          s.Z *= __expf(sc * d[3]);
-          ++it32;
-        }
-        // ---- FP64 phase.  The first step is a simplified Newton step with
-        // the FP32 Hessian H of the current point (its relative error ~1e-7
-        // times a residual ~1e-6 leaves ~1e-13); full FP64 Newton steps
-        // follow only if the residual is still above tol.
-        FS<double> t{(double)s.a, (double)s.X, (double)s.Y, (double)s.Z};
-        bool ok = false;
-        if (__builtin_isfinite(t.a) && t.a > 0.0 && t.X > 0.0 && t.Y > 0.0 && t.Z > 0.0 &&
-            __builtin_isfinite(t.X) && __builtin_isfinite(t.Y) && __builtin_isfinite(t.Z)) {
-          double gd[4], Hd[10], dd[4];
-          fsys_grad<double>(t, u1, u2, e, gd);
-          res = resid(gd);
-          if (res <= a.tol) {
-            ok = true;
-          } else if (res < 1e-4 && it64 < a.max64) {
-            float gf[4] = {(float)gd[0], (float)gd[1], (float)gd[2], (float)gd[3]}, df[4];
-            fsolve<float>(H, gf, df);
-            t.a *= exp_step((double)df[0]);
-            t.X *= exp_step((double)df[1]);
-            t.Y *= exp_step((double)df[2]);
-            t.Z *= exp_step((double)df[3]);
-            ++it64;
-            fsys_grad<double>(t, u1, u2, e, gd);
-            res = resid(gd);
-            ok = res <= a.tol;
-          }
-          for (; !ok;) {
-            fsys<double>(t, u1, u2, e, gd, Hd);
-            res = resid(gd);
-            if (res <= a.tol) { ok = true; break; }
-            if (it64 >= a.max64 || !(res < 1e-2)) break;
-            fsolve<double>(Hd, gd, dd);
-            t.a *= exp_step(dd[0]);
-            t.X *= exp_step(dd[1]);
-            t.Y *= exp_step(dd[2]);
-            t.Z *= exp_step(dd[3]);
-            ++it64;
-          }
-        }
-        if (ok) {
-          write_mu(a, i, rho, t);
-          if (a.status) a.status[i] = 0;
-          maxres = fmax(maxres, res);
-        } else {
-          const uint32_t slot = atomicAdd(&a.ctr[0], 1u);
-          a.fail_list[slot] = (uint32_t)i;
-        }
-        sum32 += (uint32_t)it32;
-        sum64 += (uint32_t)it64;
+      bool failed = false;
+      solve_site<START>(a, i, rho, u1, u2, e, it32, it64, ninf, maxres, failed);
+      if (failed) {
+        const uint32_t slot = atomicAdd(&a.ctr[0], 1u);
+        a.fail_list[slot] = (uint32_t)i;
       }
+      sum32 += (uint32_t)it32;
+      sum64 += (uint32_t)it64;
       if (a.iters) a.iters[i] = (uint8_t)(it32 + it64 < 255 ? it32 + it64 : 255);
     }
-    // histogram of updates: one pass per distinct value in the wavefront
-    const int tot = it32 + it64 < 15 ? it32 + it64 : 15;
-    unsigned long long rem = __ballot(live);
-    while (rem) {
-      const int src = __ffsll((long long)rem) - 1;
-      const int b = __shfl(tot, src);
-      const unsigned long long m = __ballot(live && tot == b);
-      if (lane == 0) atomicAdd(&sh.hist[b], (uint32_t)__popcll(m));
-      rem &= ~m;
-    }
+    solve_hist(sh, live, it32 + it64);
   }
-  // wavefront reductions, then one LDS atomic per wavefront
-  #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    sum32 += __shfl_xor(sum32, off);
-    sum64 += __shfl_xor(sum64, off);
-    ninf += __shfl_xor(ninf, off);
-    maxres = fmax(maxres, __shfl_xor(maxres, off));
-  }
-  if (lane == 0) {
-    atomicAdd(&sh.sum32, sum32);
-    atomicAdd(&sh.sum64, sum64);
-    atomicAdd(&sh.infeasible, ninf);
-    atomicMax(&sh.maxres_bits, (unsigned long long)__double_as_longlong(maxres));
-  }
-  __syncthreads();
-  if (threadIdx.x < 16 && sh.hist[threadIdx.x]) atomicAdd(&a.stats->hist[threadIdx.x], (unsigned long long)sh.hist[threadIdx.x]);
-  if (threadIdx.x == 16) {
-    atomicAdd(&a.stats->sum32, (unsigned long long)sh.sum32);
-    atomicAdd(&a.stats->sum64, (unsigned long long)sh.sum64);
-    atomicAdd(&a.stats->infeasible, (unsigned long long)sh.infeasible);
-    atomicMax(&a.stats->maxres_bits, sh.maxres_bits);
-  }
+  solve_flush(a, sh, sum32, sum64, ninf, maxres);
 }
 
 // FP64 damped-Newton fallback over the compacted failures
@@ -275,6 +122,16 @@ __global__ void k_fstar_clear(FstarArgs a) {
     a.stats->fallback = a.stats->failed = 0;
     a.stats->maxres_bits = 0;
   }
+}
+
+hipError_t launch_fstar_clear(const FstarArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_fstar_clear, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fstar_fallback(const FstarArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_fstar_fallback, dim3(64), dim3(64), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s) {

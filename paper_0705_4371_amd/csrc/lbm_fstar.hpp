@@ -33,6 +33,10 @@ struct FstarArgs {
 };
 
 hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s);
+// the statistics clear and the damped fallback over the listed failures
+// (the time step's lattice variant launches its own solve between them)
+hipError_t launch_fstar_clear(const FstarArgs& a, hipStream_t s);
+hipError_t launch_fstar_fallback(const FstarArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // MLP 4 -> 64 -> 64 -> 4 (SiLU), BF16 MFMA with FP32 accumulation

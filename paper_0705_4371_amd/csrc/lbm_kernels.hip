@@ -24,6 +24,7 @@
 
 #include "lbm_device.hpp"
 #include "lbm_fstar_dev.hpp"
+#include "lbm_fstar_site.hpp"
 #include "lbm_launch.hpp"
 
 namespace lbm {
@@ -984,6 +985,55 @@ __global__ __launch_bounds__(STEP_TX) void k_moments_M(StepArgs a) {
   a.Mbuf[3 * N + s] = e2;
 }
 
+// f*_M time step, first part, for the starts that need no network: the pull
+// of f(x, t) on the step kernel's row segments, its FP64 moments and the
+// per-site Newton solve in one kernel (the moments never go to HBM); the
+// moments of a site whose first pass failed are written for the fallback.
+template <typename T, bool PULL, int START>
+__global__ __launch_bounds__(STEP_TX) void k_fstar_lattice(StepArgs s, FstarArgs a) {
+  __shared__ SolveAcc sh;
+  if (threadIdx.x < sizeof(SolveAcc) / 4) ((uint32_t*)&sh)[threadIdx.x] = 0;
+  __syncthreads();
+  const T* __restrict__ A = (const T*)s.A;
+  const Geom& g = s.g;
+  const int64_t N = g.nx * g.ny;
+  uint32_t sum32 = 0, sum64 = 0, ninf = 0;
+  double maxres = 0.0;
+  // row segments in a grid-stride loop (uniform trip count per block)
+  for (int64_t bb = blockIdx.x; bb < s.nblocks; bb += gridDim.x) {
+    const int64_t b = xcd_remap(bb, s.nblocks);
+    const int64_t y = b / s.ntx;
+    const int64_t x0 = (b - y * s.ntx) * STEP_TX;
+    const int64_t x = x0 + threadIdx.x;
+    const bool fluid = x < g.nx && !is_solid(g, x, y);
+    T f[9];
+    load_segment_site<T, 9, PULL>(A, g, x0, x, y, fluid, f);
+    int it32 = 0, it64 = 0;
+    if (fluid) {
+      double fd[9];
+      #pragma unroll
+      for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
+      const Moments<9, double> m = moments<9, double>(fd);
+      const double rho = m.rho, u1 = m.jx / rho, u2 = m.jy / rho, e = m.e2 / rho;
+      const int64_t i = x + y * g.nx;
+      bool failed = false;
+      solve_site<START>(a, i, rho, u1, u2, e, it32, it64, ninf, maxres, failed);
+      if (failed) {
+        s.Mbuf[i] = m.rho;
+        s.Mbuf[N + i] = m.jx;
+        s.Mbuf[2 * N + i] = m.jy;
+        s.Mbuf[3 * N + i] = m.e2;
+        const uint32_t slot = atomicAdd(&a.ctr[0], 1u);
+        a.fail_list[slot] = (uint32_t)i;
+      }
+      sum32 += (uint32_t)it32;
+      sum64 += (uint32_t)it64;
+    }
+    solve_hist(sh, fluid, it32 + it64);
+  }
+  solve_flush(a, sh, sum32, sum64, ninf, maxres);
+}
+
 __global__ __launch_bounds__(256) void k_init_M_moments(StepArgs a, const double* __restrict__ rho0,
                                                         const double* __restrict__ u0,
                                                         const double* __restrict__ twoE0) {
@@ -1146,6 +1196,26 @@ hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s) {
     else hipLaunchKernelGGL((k_moments_M<float, false>), dim3(gr), dim3(256), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <typename T, bool PULL>
+static void fstar_lattice_t(const StepArgs& a, const FstarArgs& fa, int start, unsigned gr, hipStream_t s) {
+  if (start == START_CLOSED) hipLaunchKernelGGL((k_fstar_lattice<T, PULL, START_CLOSED>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
+  else if (start == START_PREV) hipLaunchKernelGGL((k_fstar_lattice<T, PULL, START_PREV>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
+  else hipLaunchKernelGGL((k_fstar_lattice<T, PULL, START_REST>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
+}
+
+hipError_t launch_fstar_lattice(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s) {
+  hipError_t e = launch_fstar_clear(fa, s);
+  if (e != hipSuccess) return e;
+  // capped grid, a multiple of 8 (the XCD remap), so that the statistics
+  // atomics stay few
+  const unsigned gr = (unsigned)(a.nblocks < FSTAR_MAX_BLOCKS ? a.nblocks : FSTAR_MAX_BLOCKS);
+  if (a.prec == 1) { if (pull) fstar_lattice_t<double, true>(a, fa, start, gr, s); else fstar_lattice_t<double, false>(a, fa, start, gr, s); }
+  else { if (pull) fstar_lattice_t<float, true>(a, fa, start, gr, s); else fstar_lattice_t<float, false>(a, fa, start, gr, s); }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_fstar_fallback(fa, s);
 }
 
 hipError_t launch_init_M_moments(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,

@@ -26,7 +26,8 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-STEP_SOURCES = ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar_dev.hpp")
+STEP_SOURCES = ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar.hpp", "lbm_fstar_dev.hpp",
+                "lbm_fstar_site.hpp")
 
 
 def kernel_source_hash() -> str:
