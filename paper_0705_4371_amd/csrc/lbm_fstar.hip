@@ -79,7 +79,8 @@ __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
     const bool live = i < n;
     int it32 = 0, it64 = 0;
     if (live) {
-      const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
+      const double rho = a.M[i], ir = 1.0 / rho;
+      const double u1 = a.M[n + i] * ir, u2 = a.M[2 * n + i] * ir, e = a.M[3 * n + i] * ir;
       bool failed = false;
       solve_site<START>(a, i, rho, u1, u2, e, it32, it64, ninf, maxres, failed);
       if (failed) {

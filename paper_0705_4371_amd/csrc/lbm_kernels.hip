@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(STEP_TX) void k_fstar_lattice(StepArgs s, FstarArgs
       #pragma unroll
       for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
       const Moments<9, double> m = moments<9, double>(fd);
-      const double rho = m.rho, u1 = m.jx / rho, u2 = m.jy / rho, e = m.e2 / rho;
+      const double rho = m.rho, ir = 1.0 / rho, u1 = m.jx * ir, u2 = m.jy * ir, e = m.e2 * ir;
       const int64_t i = x + y * g.nx;
       bool failed = false;
       solve_site<START>(a, i, rho, u1, u2, e, it32, it64, ninf, maxres, failed);
