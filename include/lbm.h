@@ -107,7 +107,7 @@ typedef struct lbm_es_stats {
                             the rest start) plus infeasible sites (closed form)   */
   int64_t total_selected;/* all steps since init                                   */
   int64_t nonfinite;     /* sticky: a step met non-finite populations              */
-  int64_t newton_updates;/* last step, f*_M only: Newton updates over all sites    */
+  int64_t newton_updates;/* last step, f*_M only: Newton updates over fluid sites  */
   double kth_dS;         /* last step: smallest selected Delta S (0 if none)       */
   double max_dS;         /* last step: largest Delta S above delta (0 if none)     */
   double mass, mom[2], energy; /* FP64 sums over fluid sites of rho, rho u1,
