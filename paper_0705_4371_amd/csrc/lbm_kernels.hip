@@ -2,17 +2,21 @@
 // time step (Sec. 3.2, eq. (ESLB) of Sec. 4.1, boundary rules of Sec. 4.2).
 //
 // One time step is four kernels on one stream:
-//   k_step   fused pull-stream + boundary rules + moments + f* + FP32 Delta S
-//            screen + LBGK collision + write; screened sites are appended to
-//            a list (one atomic per wavefront).             (HBM bound)
-//   k_rank   FP64 Delta S of the screened sites; sites with Delta S > delta
-//            become candidates (site, Delta S) and feed a 2^15-bin histogram
-//            of the top bits of Delta S.                    (O(#screened))
-//   k_select one workgroup: "fewer than k: all of them", otherwise the k
-//            largest (Delta S descending, site ascending) by the histogram
-//            bin and an 8-bit radix refinement of the remaining 80 key bits.
-//   k_reset  selected sites: re-pull f(x, t), recompute f*, overwrite the
-//            collided values with f* (return to quasiequilibrium).
+//   k_step      fused pull-stream + boundary rules + moments + f* + FP32
+//               Delta S screen + LBGK collision + write; screened sites are
+//               appended to a list (one atomic per workgroup).  (HBM bound)
+//   k_rank      FP64 Delta S of the screened sites; sites with Delta S > delta
+//               become candidates (site, Delta S); with more than k screened
+//               sites a 2^15-bin histogram of the top key bits is built.
+//   k_partition "fewer than k: all of them", otherwise the keys above the
+//               histogram bin b* of the k-th largest key are selected and
+//               returned to quasiequilibrium (re-pull f(x, t), recompute f*,
+//               overwrite the collided values); the keys in b* are listed.
+//   k_refine    one workgroup: radix passes over the listed keys find the
+//               rest of the k largest; they are reset; statistics.
+// (LBM_SELECT_ONE replaces the last three by k_select_one.)  For the
+// entropic f*_M quasiequilibrium the per-site solve (k_fstar_lattice) runs
+// before k_step.
 //
 // State layout: tiles of 64 sites of a row, [ny][pitch/64][Q][64] of T
 // (float or double), pitch = nx rounded up to 64 (see sidx).  The state
