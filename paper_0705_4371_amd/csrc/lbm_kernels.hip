@@ -162,10 +162,63 @@ __device__ __forceinline__ void load_segment_site(const T* __restrict__ A, const
 // ---------------------------------------------------------------------------
 // k_step
 // ---------------------------------------------------------------------------
+// monitoring point (Sec. 4.2): density and velocity of f(x, t), one sample
+// per step into a ring (only the probe's lane ever calls it)
+template <int Q, typename T>
+__device__ __forceinline__ void probe_sample(const StepArgs& a, const Moments<Q, T>& m) {
+  const unsigned long long n = *a.probe_n;
+  const int64_t j = (int64_t)(n % (unsigned long long)a.probe_cap);
+  a.probe_buf[j] = (double)m.rho;
+  a.probe_buf[a.probe_cap + j] = (double)m.jx / (double)m.rho;
+  a.probe_buf[2 * a.probe_cap + j] = (double)m.jy / (double)m.rho;
+  *a.probe_n = n + 1;
+}
+
+// FP32 screen of Delta S for the entropic quasiequilibria (artanh series,
+// with a margin); screened sites are re-ranked in FP64
+template <int Q, typename T>
+__device__ __forceinline__ bool screen_entropic(const StepArgs& a, const T* f, const T* fs, T rho) {
+  float ff[Q], fsf[Q];
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) { ff[i] = (float)f[i]; fsf[i] = (float)fs[i]; }
+  const float ds = dS_screen<Q>(ff, fsf);
+  const float thr = a.thr_a - a.thr_b * __builtin_sqrtf(fmaxf((float)rho, 0.0f));
+  return !(ds < thr);
+}
+
+// LBGK collision f' = f + 2 beta (f* - f) (eq. (lbgkLB)), or ELBM
+// f' = f + alpha beta (f* - f) (eq. (elbmLB)), written at the origin site
+// with non-temporal stores (nothing reads it again in this step)
+template <typename T, int Q, bool ELBM>
+__device__ __forceinline__ void collide_store(const StepArgs& a, int64_t x, int64_t y, const T* f, const T* fs) {
+  T* __restrict__ B = (T*)a.B;
+  T b2 = T(a.g.beta2);
+  if constexpr (ELBM) {
+    double fd[Q], fsd[Q];
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) { fd[i] = (double)f[i]; fsd[i] = (double)fs[i]; }
+    b2 = T(0.5 * a.g.beta2 * elbm_alpha<Q>(fd, fsd));
+  }
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(T(f[i] + b2 * (fs[i] - f[i])), &B[sidx<Q>(a.g, x, y, i)]);
+}
+
+// the screened sites of the workgroup are appended with one atomic, and the
+// sticky non-finite flag is raised (every thread of the block calls this)
+__device__ __forceinline__ void append_screened(const StepArgs& a, bool scr, uint32_t site, bool bad) {
+  if (__syncthreads_or(scr)) {
+    __shared__ uint32_t s_cnt[4], s_base;
+    const uint32_t slot = block_append(scr, &a.ctr[C_SCREEN], s_cnt, &s_base);
+    if (scr) a.screen[slot] = site;
+  }
+  // once the flag is set, waves only read it (no atomic storm on one word)
+  if (__ballot(bad) && (threadIdx.x & 63) == 0 && __atomic_load_n(&a.ctr[C_NONFINITE], __ATOMIC_RELAXED) == 0u)
+    atomicOr(&a.ctr[C_NONFINITE], 1u);
+}
+
 template <typename T, int Q, int QE, bool PULL, bool ELBM = false>
 __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   const T* __restrict__ A = (const T*)a.A;
-  T* __restrict__ B = (T*)a.B;
   const Geom& g = a.g;
   const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
   const int64_t y = b / a.ntx;
@@ -177,16 +230,7 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   load_segment_site<T, Q, PULL>(A, g, x0, x, y, fluid, f);
 
   const Moments<Q, T> m = moments<Q, T>(f);
-  // monitoring point (Sec. 4.2): density and velocity of f(x, t), one sample
-  // per step into a ring (only the probe's lane ever touches it)
-  if (fluid && x + y * g.nx == a.probe) {
-    const unsigned long long n = *a.probe_n;
-    const int64_t j = (int64_t)(n % (unsigned long long)a.probe_cap);
-    a.probe_buf[j] = (double)m.rho;
-    a.probe_buf[a.probe_cap + j] = (double)m.jx / (double)m.rho;
-    a.probe_buf[2 * a.probe_cap + j] = (double)m.jy / (double)m.rho;
-    *a.probe_n = n + 1;
-  }
+  if (fluid && x + y * g.nx == a.probe) probe_sample<Q, T>(a, m);
   T fs[Q], pb[Q];
   const T inv = inv_of(m.rho);
   const T ux = m.jx * inv, uy = m.jy * inv;
@@ -200,53 +244,24 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
     }
   }
 
-  // FP32 screen of Delta S (an upper bound, or an estimate with a margin);
-  // screened sites are re-ranked in FP64 by k_rank
+  // FP32 screen of Delta S (an upper bound for the polynomial QE, an
+  // estimate with a margin otherwise); screened sites are re-ranked in FP64
   bool scr = false;
   if (g.ds_on && fluid) {
-    float ff[Q], fsf[Q];
-    #pragma unroll
-    for (int i = 0; i < Q; ++i) { ff[i] = (float)f[i]; fsf[i] = (float)fs[i]; }
-    float ds;
     if constexpr (QE == QE_POLY) {
-      float pf[Q];
+      float ff[Q], fsf[Q], pf[Q];
       #pragma unroll
-      for (int i = 0; i < Q; ++i) pf[i] = (float)pb[i];
-      ds = dS_bound_poly<Q>(ff, fsf, pf, (float)inv);
+      for (int i = 0; i < Q; ++i) { ff[i] = (float)f[i]; fsf[i] = (float)fs[i]; pf[i] = (float)pb[i]; }
+      const float ds = dS_bound_poly<Q>(ff, fsf, pf, (float)inv);
+      const float thr = a.thr_a - a.thr_b * __builtin_sqrtf(fmaxf((float)m.rho, 0.0f));
+      scr = !(ds < thr);
     } else {
-      ds = dS_screen<Q>(ff, fsf);
+      scr = screen_entropic<Q, T>(a, f, fs, m.rho);
     }
-    const float thr = a.thr_a - a.thr_b * __builtin_sqrtf(fmaxf((float)m.rho, 0.0f));
-    scr = !(ds < thr);
   }
 
-  // LBGK collision f' = f + 2 beta (f* - f) (eq. (lbgkLB)), or ELBM
-  // f' = f + alpha beta (f* - f) (eq. (elbmLB)); written at the origin site
-  // with non-temporal stores (nothing reads it again in this step)
-  if (fluid) {
-    T b2 = T(g.beta2);
-    if constexpr (ELBM) {
-      double fd[Q], fsd[Q];
-      #pragma unroll
-      for (int i = 0; i < Q; ++i) { fd[i] = (double)f[i]; fsd[i] = (double)fs[i]; }
-      b2 = T(0.5 * g.beta2 * elbm_alpha<Q>(fd, fsd));
-    }
-    #pragma unroll
-    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(T(f[i] + b2 * (fs[i] - f[i])), &B[sidx<Q>(g, x, y, i)]);
-  }
-
-  // append screened sites: one atomic per workgroup that has any
-  if (__syncthreads_or(scr)) {
-    __shared__ uint32_t s_cnt[4], s_base;
-    const uint32_t slot = block_append(scr, &a.ctr[C_SCREEN], s_cnt, &s_base);
-    if (scr) a.screen[slot] = (uint32_t)(x + y * g.nx);
-  }
-
-  // sticky flag for non-finite populations (a non-finite f gives a non-finite
-  // rho); once it is set, waves only read it (no atomic storm on one word)
-  if (__ballot(fluid && !__builtin_isfinite(m.rho)) && (threadIdx.x & 63) == 0 &&
-      __atomic_load_n(&a.ctr[C_NONFINITE], __ATOMIC_RELAXED) == 0u)
-    atomicOr(&a.ctr[C_NONFINITE], 1u);
+  if (fluid) collide_store<T, Q, ELBM>(a, x, y, f, fs);
+  append_screened(a, scr, (uint32_t)(x + y * g.nx), fluid && !__builtin_isfinite(m.rho));
 }
 
 // ---------------------------------------------------------------------------
