@@ -182,6 +182,18 @@ int lbm_ehrenfest_stats(lbm_ctx* ctx, lbm_es_stats* out, int64_t* sel, double* s
 int lbm_candidates(lbm_ctx* ctx, int64_t* sites, double* dS, int64_t cap, int64_t* n);
 
 /*
+ * f*_M solver of a context (LBM_QE_ENTROPIC_M): residual target tol of the
+ * FP64 phase (default 1e-10), target tol32 of the FP32 phase (2e-6) and the
+ * update budgets of the first pass (max32 = 16, max64 = 6).  A site that
+ * misses tol within the budgets is solved again by the damped FP64 Newton
+ * fallback from the rest start (Sec. 3.3's multipliers; counted in
+ * lbm_es_stats.n_fallback).  Returns LBM_E_INVAL for another quasiequilibrium
+ * or out-of-range values (0 <= max32 <= 64, 1 <= max64 <= 64); waits for the
+ * context's stream (captured step graphs are rebuilt).
+ */
+int lbm_set_fstar_tolerance(lbm_ctx* ctx, double tol, double tol32, int32_t max32, int32_t max64);
+
+/*
  * Kernel timing for measurement: with on != 0, lbm_step launches the step
  * kernels directly (no graph replay) and brackets each fused step kernel
  * with HIP events on the context's stream; lbm_kernel_time synchronises and

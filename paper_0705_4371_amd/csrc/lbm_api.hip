@@ -246,22 +246,18 @@ static StepArgs args_for(const lbm_ctx* c, int src, int dst) {
   return a;
 }
 
-// one time step from buffer src into buffer dst; for the f*_M
-// quasiequilibrium the moments, the (optional) network start and the Newton
-// solve for every site run first
+// one time step from buffer src into buffer dst.  For the f*_M
+// quasiequilibrium with a network start the moments of every site go to
+// memory, the network and the Newton solve run, then the step kernel; the
+// other starts solve and collide in one kernel.
 static hipError_t step_once(const lbm_ctx* c, int src, int dst, bool pull, hipStream_t s, hipEvent_t e0,
                             hipEvent_t e1) {
   const StepArgs a = args_for(c, src, dst);
   if (c->cfg.qe == LBM_QE_ENTROPIC_M) {
-    hipError_t e;
-    if (c->fkind == START_WARM) {
-      // the network needs the moments of every site in memory
-      e = launch_moments_M(a, pull, s);
-      if (e == hipSuccess) e = launch_mlp_warm(c->cfg.net->params, c->cfg.net->norm, c->Mbuf, c->N, c->warm, s);
-      if (e == hipSuccess) e = launch_fstar(c->fa, c->fkind, s);
-    } else {
-      e = launch_fstar_lattice(a, c->fa, c->fkind, pull, s);
-    }
+    if (c->fkind != START_WARM) return launch_fstep(a, c->fa, c->fkind, pull, s, e0, e1);
+    hipError_t e = launch_moments_M(a, pull, s);
+    if (e == hipSuccess) e = launch_mlp_warm(c->cfg.net->params, c->cfg.net->norm, c->Mbuf, c->N, c->warm, s);
+    if (e == hipSuccess) e = launch_fstar(c->fa, c->fkind, s);
     if (e != hipSuccess) return e;
   }
   return launch_step(a, pull, s, e0, e1);
@@ -629,6 +625,20 @@ static int drop_graphs(lbm_ctx* c) {
     c->gexec[p] = nullptr;
     c->graph[p] = nullptr;
   }
+  return LBM_OK;
+}
+
+int lbm_set_fstar_tolerance(lbm_ctx* c, double tol, double tol32, int32_t max32, int32_t max64) {
+  if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  if (c->cfg.qe != LBM_QE_ENTROPIC_M) return fail(LBM_E_INVAL, "the context does not use LBM_QE_ENTROPIC_M");
+  if (!(tol > 0.0) || !(tol32 > 0.0) || max32 < 0 || max64 < 1 || max32 > 64 || max64 > 64)
+    return fail(LBM_E_INVAL, "need tol > 0, tol32 > 0, 0 <= max32 <= 64, 1 <= max64 <= 64");
+  int rc = drop_graphs(c);
+  if (rc) return rc;
+  c->fa.tol = tol;
+  c->fa.tol32 = (float)tol32;
+  c->fa.max32 = max32;
+  c->fa.max64 = max64;
   return LBM_OK;
 }
 

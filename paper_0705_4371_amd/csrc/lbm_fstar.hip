@@ -23,46 +23,6 @@
 
 namespace lbm {
 
-// FP64 damped Newton from the rest start; returns iterations (negative on failure)
-__device__ int newton64_damped(double u1, double u2, double e, double tol, int max_it, FS<double>& s,
-                               double& res) {
-  s.a = 4.0 / 9.0;
-  s.X = 1.0;
-  s.Y = 1.0;
-  s.Z = 0.25;
-  double g[4], H[10], d[4];
-  for (int it = 0; it <= max_it; ++it) {
-    fsys<double>(s, u1, u2, e, g, H);
-    res = resid(g);
-    if (res <= tol) return it;
-    if (it == max_it) break;
-    fsolve<double>(H, g, d);
-    double t = 1.0;
-    if (res > 1e-3) {
-      // Armijo on phi/rho = a n_x n_y - (ln a, ln X, ln Y, ln Z) . (1, u1, u2, e)
-      const double phi0 = H[0] - (::log(s.a) + ::log(s.X) * u1 + ::log(s.Y) * u2 + ::log(s.Z) * e);
-      const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2] + g[3] * d[3];
-      for (int ls = 0; ls < 60; ++ls) {
-        FS<double> q;
-        q.a = s.a * ::exp(t * d[0]);
-        q.X = s.X * ::exp(t * d[1]);
-        q.Y = s.Y * ::exp(t * d[2]);
-        q.Z = s.Z * ::exp(t * d[3]);
-        double gq[4], Hq[10];
-        fsys<double>(q, u1, u2, e, gq, Hq);
-        const double phi = Hq[0] - (::log(q.a) + ::log(q.X) * u1 + ::log(q.Y) * u2 + ::log(q.Z) * e);
-        if (phi <= phi0 + 1e-4 * t * slope) break;
-        t *= 0.5;
-      }
-    }
-    s.a *= ::exp(t * d[0]);
-    s.X *= ::exp(t * d[1]);
-    s.Y *= ::exp(t * d[2]);
-    s.Z *= ::exp(t * d[3]);
-  }
-  return -1;
-}
-
 template <int START>
 __global__ __launch_bounds__(256) void k_fstar(FstarArgs a) {
   __shared__ SolveAcc sh;

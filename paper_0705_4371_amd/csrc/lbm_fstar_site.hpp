@@ -26,6 +26,46 @@ __device__ __forceinline__ void write_mu(const FstarArgs& a, int64_t i, double r
   }
 }
 
+// FP64 damped Newton from the rest start; returns iterations (negative on failure)
+__device__ inline int newton64_damped(double u1, double u2, double e, double tol, int max_it, FS<double>& s,
+                               double& res) {
+  s.a = 4.0 / 9.0;
+  s.X = 1.0;
+  s.Y = 1.0;
+  s.Z = 0.25;
+  double g[4], H[10], d[4];
+  for (int it = 0; it <= max_it; ++it) {
+    fsys<double>(s, u1, u2, e, g, H);
+    res = resid(g);
+    if (res <= tol) return it;
+    if (it == max_it) break;
+    fsolve<double>(H, g, d);
+    double t = 1.0;
+    if (res > 1e-3) {
+      // Armijo on phi/rho = a n_x n_y - (ln a, ln X, ln Y, ln Z) . (1, u1, u2, e)
+      const double phi0 = H[0] - (::log(s.a) + ::log(s.X) * u1 + ::log(s.Y) * u2 + ::log(s.Z) * e);
+      const double slope = g[0] * d[0] + g[1] * d[1] + g[2] * d[2] + g[3] * d[3];
+      for (int ls = 0; ls < 60; ++ls) {
+        FS<double> q;
+        q.a = s.a * ::exp(t * d[0]);
+        q.X = s.X * ::exp(t * d[1]);
+        q.Y = s.Y * ::exp(t * d[2]);
+        q.Z = s.Z * ::exp(t * d[3]);
+        double gq[4], Hq[10];
+        fsys<double>(q, u1, u2, e, gq, Hq);
+        const double phi = Hq[0] - (::log(q.a) + ::log(q.X) * u1 + ::log(q.Y) * u2 + ::log(q.Z) * e);
+        if (phi <= phi0 + 1e-4 * t * slope) break;
+        t *= 0.5;
+      }
+    }
+    s.a *= ::exp(t * d[0]);
+    s.X *= ::exp(t * d[1]);
+    s.Y *= ::exp(t * d[2]);
+    s.Z *= ::exp(t * d[3]);
+  }
+  return -1;
+}
+
 // Statistics are accumulated per thread over its sites, reduced per
 // wavefront with shuffles and per block in LDS, and added to the global
 // counters once per block (the grid is capped so that these atomics stay few).
@@ -40,18 +80,24 @@ constexpr int FSTAR_MAX_BLOCKS = 2048;
 // One site of the solve: rho and u1, u2, e = 2E/rho of its moments; mu
 // (or the state) written for a converged or infeasible site; `failed` set
 // when the first pass missed the tolerance (the caller lists the site for the
-// damped fallback).  it32 / it64: Newton updates of the two phases.
+// damped fallback).  it32 / it64: Newton updates of the two phases.  With
+// st non-null the written state is also returned there in product form
+// (A rho, X, Y, Z; NaN for a site with no quasiequilibrium).
 template <int START>
 __device__ __forceinline__ void solve_site(const FstarArgs& a, int64_t i, double rho, double u1, double u2, double e,
-                                           int& it32, int& it64, uint32_t& ninf, double& maxres, bool& failed) {
+                                           int& it32, int& it64, uint32_t& ninf, double& maxres, bool& failed,
+                                           double* st = nullptr) {
   const int64_t n = a.n;
   double res = 0.0;
   if (!feasible(rho, u1, u2, e)) {
     ninf++;
     if (__builtin_fabs(u1) < 1.0 && __builtin_fabs(u2) < 1.0 && rho > 0.0) {
-      write_mu(a, i, rho, closed_form<double>(u1, u2));
+      const FS<double> c = closed_form<double>(u1, u2);
+      write_mu(a, i, rho, c);
+      if (st) { st[0] = c.a * rho; st[1] = c.X; st[2] = c.Y; st[3] = c.Z; }
     } else {
       for (int c = 0; c < 4; ++c) a.mu[c * n + i] = __builtin_nan("");
+      if (st) for (int c = 0; c < 4; ++c) st[c] = __builtin_nan("");
     }
     if (a.status) a.status[i] = 2;
   } else {
@@ -140,6 +186,7 @@ __device__ __forceinline__ void solve_site(const FstarArgs& a, int64_t i, double
     }
     if (ok) {
       write_mu(a, i, rho, t);
+      if (st) { st[0] = t.a * rho; st[1] = t.X; st[2] = t.Y; st[3] = t.Z; }
       if (a.status) a.status[i] = 0;
       maxres = fmax(maxres, res);
     } else {

@@ -15,8 +15,10 @@
 //   k_refine    one workgroup: radix passes over the listed keys find the
 //               rest of the k largest; they are reset; statistics.
 // (LBM_SELECT_ONE replaces the last three by k_select_one.)  For the
-// entropic f*_M quasiequilibrium the per-site solve (k_fstar_lattice) runs
-// before k_step.
+// entropic f*_M quasiequilibrium k_fstep takes the place of k_step: it also
+// runs the per-site Newton solve, and k_fstep_fallback solves and collides
+// the few sites whose first pass failed (with a network start the solve
+// runs before k_step instead).
 //
 // State layout: tiles of 64 sites of a row, [ny][pitch/64][Q][64] of T
 // (float or double), pitch = nx rounded up to 64 (see sidx).  The state
@@ -1004,12 +1006,14 @@ __global__ __launch_bounds__(STEP_TX) void k_moments_M(StepArgs a) {
   a.Mbuf[3 * N + s] = e2;
 }
 
-// f*_M time step, first part, for the starts that need no network: the pull
-// of f(x, t) on the step kernel's row segments, its FP64 moments and the
-// per-site Newton solve in one kernel (the moments never go to HBM); the
-// moments of a site whose first pass failed are written for the fallback.
-template <typename T, bool PULL, int START>
-__global__ __launch_bounds__(STEP_TX) void k_fstar_lattice(StepArgs s, FstarArgs a) {
+// f*_M time step for the starts that need no network (rest, closed form,
+// previous step): the pull of f(x, t) on the step kernel's row segments, its
+// FP64 moments, the per-site Newton solve, the FP32 Delta S screen and the
+// collision in one kernel (a grid-stride loop with a uniform trip count per
+// block).  A site whose first pass failed is listed with its moments and is
+// solved and collided by k_fstep_fallback.
+template <typename T, bool PULL, int START, bool ELBM>
+__global__ __launch_bounds__(STEP_TX) void k_fstep(StepArgs s, FstarArgs a) {
   __shared__ SolveAcc sh;
   if (threadIdx.x < sizeof(SolveAcc) / 4) ((uint32_t*)&sh)[threadIdx.x] = 0;
   __syncthreads();
@@ -1018,39 +1022,77 @@ __global__ __launch_bounds__(STEP_TX) void k_fstar_lattice(StepArgs s, FstarArgs
   const int64_t N = g.nx * g.ny;
   uint32_t sum32 = 0, sum64 = 0, ninf = 0;
   double maxres = 0.0;
-  // row segments in a grid-stride loop (uniform trip count per block)
   for (int64_t bb = blockIdx.x; bb < s.nblocks; bb += gridDim.x) {
     const int64_t b = xcd_remap(bb, s.nblocks);
     const int64_t y = b / s.ntx;
     const int64_t x0 = (b - y * s.ntx) * STEP_TX;
     const int64_t x = x0 + threadIdx.x;
+    const int64_t i = x + y * g.nx;
     const bool fluid = x < g.nx && !is_solid(g, x, y);
     T f[9];
     load_segment_site<T, 9, PULL>(A, g, x0, x, y, fluid, f);
+    const Moments<9, T> m = moments<9, T>(f);
+    if (fluid && i == s.probe) probe_sample<9, T>(s, m);
     int it32 = 0, it64 = 0;
+    bool scr = false;
     if (fluid) {
       double fd[9];
       #pragma unroll
-      for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
-      const Moments<9, double> m = moments<9, double>(fd);
-      const double rho = m.rho, ir = 1.0 / rho, u1 = m.jx * ir, u2 = m.jy * ir, e = m.e2 * ir;
-      const int64_t i = x + y * g.nx;
+      for (int q = 0; q < 9; ++q) fd[q] = (double)f[q];
+      const Moments<9, double> md = moments<9, double>(fd);
+      const double rho = md.rho, ir = 1.0 / rho, u1 = md.jx * ir, u2 = md.jy * ir, e = md.e2 * ir;
       bool failed = false;
-      solve_site<START>(a, i, rho, u1, u2, e, it32, it64, ninf, maxres, failed);
+      double st[4];
+      solve_site<START>(a, i, rho, u1, u2, e, it32, it64, ninf, maxres, failed, st);
       if (failed) {
-        s.Mbuf[i] = m.rho;
-        s.Mbuf[N + i] = m.jx;
-        s.Mbuf[2 * N + i] = m.jy;
-        s.Mbuf[3 * N + i] = m.e2;
+        s.Mbuf[i] = md.rho;
+        s.Mbuf[N + i] = md.jx;
+        s.Mbuf[2 * N + i] = md.jy;
+        s.Mbuf[3 * N + i] = md.e2;
         const uint32_t slot = atomicAdd(&a.ctr[0], 1u);
         a.fail_list[slot] = (uint32_t)i;
+      } else {
+        T fs[9];
+        fstar_pop<T>((T)st[0], (T)st[1], (T)st[2], (T)st[3], fs);
+        if (g.ds_on) scr = screen_entropic<9, T>(s, f, fs, m.rho);
+        collide_store<T, 9, ELBM>(s, x, y, f, fs);
       }
       sum32 += (uint32_t)it32;
       sum64 += (uint32_t)it64;
     }
     solve_hist(sh, fluid, it32 + it64);
+    append_screened(s, scr, (uint32_t)i, fluid && !__builtin_isfinite(m.rho));
   }
   solve_flush(a, sh, sum32, sum64, ninf, maxres);
+}
+
+// the sites listed by k_fstep: FP64 damped Newton from the rest start on
+// their moments, then the same screen and collision (f(x, t) pulled again)
+template <typename T, bool PULL, bool ELBM>
+__global__ __launch_bounds__(64) void k_fstep_fallback(StepArgs s, FstarArgs a) {
+  const uint32_t nf = a.ctr[0];
+  const int64_t n = a.n;
+  const Geom& g = s.g;
+  for (uint32_t t = blockIdx.x * 64u + threadIdx.x; t < nf; t += gridDim.x * 64u) {
+    const int64_t i = a.fail_list[t];
+    const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
+    FS<double> q;
+    double res = 0.0;
+    const int it = newton64_damped(u1, u2, e, a.tol, 200, q, res);
+    write_mu(a, i, rho, q);
+    if (a.status) a.status[i] = it >= 0 ? 1 : 3;
+    atomicAdd(&a.stats->fallback, 1ull);
+    if (it < 0) atomicAdd(&a.stats->failed, 1ull);
+    else atomicMax(&a.stats->maxres_bits, (unsigned long long)__double_as_longlong(res));
+
+    const int64_t y = i / g.nx, x = i - y * g.nx;
+    T f[9], fs[9];
+    load_site<T, 9, PULL>((const T*)s.A, g, x, y, f);
+    fstar_pop<T>((T)(q.a * rho), (T)q.X, (T)q.Y, (T)q.Z, fs);
+    const Moments<9, T> m = moments<9, T>(f);
+    if (g.ds_on && screen_entropic<9, T>(s, f, fs, m.rho)) s.screen[atomicAdd(&s.ctr[C_SCREEN], 1u)] = (uint32_t)i;
+    collide_store<T, 9, ELBM>(s, x, y, f, fs);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_init_M_moments(StepArgs a, const double* __restrict__ rho0,
@@ -1091,6 +1133,18 @@ __global__ __launch_bounds__(256) void k_init_M_pops(StepArgs a) {
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// ranking, selection and reset of the screened sites
+template <typename T, int Q, int QE, bool PULL>
+static void select_t(const StepArgs& a, hipStream_t s) {
+  if (a.g.ds_on && a.one_wg) {
+    hipLaunchKernelGGL((k_select_one<T, Q, QE, PULL>), dim3(1), dim3(ONE_TX), 0, s, a);
+  } else if (a.g.ds_on) {
+    hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_partition<T, Q, QE, PULL>), dim3(PART_BLOCKS), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(256), 0, s, a);
+  }
+}
+
 template <typename T, int Q, int QE, bool PULL>
 static hipError_t step_t(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) { hipError_t e = hipEventRecord(ev0, s); if (e != hipSuccess) return e; }
@@ -1099,13 +1153,7 @@ static hipError_t step_t(const StepArgs& a, hipStream_t s, hipEvent_t ev0, hipEv
   else
     hipLaunchKernelGGL((k_step<T, Q, QE, PULL>), dim3((unsigned)a.nblocks), dim3(STEP_TX), 0, s, a);
   if (ev1) { hipError_t e = hipEventRecord(ev1, s); if (e != hipSuccess) return e; }
-  if (a.g.ds_on && a.one_wg) {
-    hipLaunchKernelGGL((k_select_one<T, Q, QE, PULL>), dim3(1), dim3(ONE_TX), 0, s, a);
-  } else if (a.g.ds_on) {
-    hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_partition<T, Q, QE, PULL>), dim3(PART_BLOCKS), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(256), 0, s, a);
-  }
+  select_t<T, Q, QE, PULL>(a, s);
   return hipGetLastError();
 }
 
@@ -1217,24 +1265,35 @@ hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, bool PULL>
-static void fstar_lattice_t(const StepArgs& a, const FstarArgs& fa, int start, unsigned gr, hipStream_t s) {
-  if (start == START_CLOSED) hipLaunchKernelGGL((k_fstar_lattice<T, PULL, START_CLOSED>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
-  else if (start == START_PREV) hipLaunchKernelGGL((k_fstar_lattice<T, PULL, START_PREV>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
-  else hipLaunchKernelGGL((k_fstar_lattice<T, PULL, START_REST>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
-}
-
-hipError_t launch_fstar_lattice(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s) {
-  hipError_t e = launch_fstar_clear(fa, s);
-  if (e != hipSuccess) return e;
+template <typename T, bool PULL, bool ELBM>
+static hipError_t fstep_t(const StepArgs& a, const FstarArgs& fa, int start, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1) {
   // capped grid, a multiple of 8 (the XCD remap), so that the statistics
   // atomics stay few
   const unsigned gr = (unsigned)(a.nblocks < FSTAR_MAX_BLOCKS ? a.nblocks : FSTAR_MAX_BLOCKS);
-  if (a.prec == 1) { if (pull) fstar_lattice_t<double, true>(a, fa, start, gr, s); else fstar_lattice_t<double, false>(a, fa, start, gr, s); }
-  else { if (pull) fstar_lattice_t<float, true>(a, fa, start, gr, s); else fstar_lattice_t<float, false>(a, fa, start, gr, s); }
-  e = hipGetLastError();
+  if (ev0) { hipError_t e = hipEventRecord(ev0, s); if (e != hipSuccess) return e; }
+  if (start == START_CLOSED) hipLaunchKernelGGL((k_fstep<T, PULL, START_CLOSED, ELBM>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
+  else if (start == START_PREV) hipLaunchKernelGGL((k_fstep<T, PULL, START_PREV, ELBM>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
+  else hipLaunchKernelGGL((k_fstep<T, PULL, START_REST, ELBM>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
+  if (ev1) { hipError_t e = hipEventRecord(ev1, s); if (e != hipSuccess) return e; }
+  hipLaunchKernelGGL((k_fstep_fallback<T, PULL, ELBM>), dim3(64), dim3(64), 0, s, a, fa);
+  select_t<T, 9, QE_ENTROPIC_M, PULL>(a, s);
+  return hipGetLastError();
+}
+
+template <typename T, bool PULL>
+static hipError_t fstep_p(const StepArgs& a, const FstarArgs& fa, int start, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1) {
+  return a.coll == 1 ? fstep_t<T, PULL, true>(a, fa, start, s, ev0, ev1)
+                     : fstep_t<T, PULL, false>(a, fa, start, s, ev0, ev1);
+}
+
+hipError_t launch_fstep(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+  hipError_t e = launch_fstar_clear(fa, s);
   if (e != hipSuccess) return e;
-  return launch_fstar_fallback(fa, s);
+  if (a.prec == 1) return pull ? fstep_p<double, true>(a, fa, start, s, ev0, ev1) : fstep_p<double, false>(a, fa, start, s, ev0, ev1);
+  return pull ? fstep_p<float, true>(a, fa, start, s, ev0, ev1) : fstep_p<float, false>(a, fa, start, s, ev0, ev1);
 }
 
 hipError_t launch_init_M_moments(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,

@@ -80,10 +80,13 @@ hipError_t launch_init(const StepArgs& a, const double* rho0, const double* u0, 
 // f*_M: moments of the current pre-collision state into a.Mbuf (solid sites
 // get the isothermal rest moments so that the solver has a feasible input)
 hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s);
-// f*_M: the statistics clear, the pull + moments + Newton solve of every
-// fluid site in one kernel (start: START_REST, START_CLOSED or START_PREV),
-// then the damped fallback
-hipError_t launch_fstar_lattice(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s);
+// f*_M time step without a network start: the statistics clear, the pull,
+// moments, Newton solve (start: START_REST, START_CLOSED or START_PREV),
+// screen and collision of every fluid site in one kernel (bracketed by
+// ev0 / ev1 when given), the damped fallback with the collision of its
+// sites, then ranking and selection
+hipError_t launch_fstep(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1);
 // f*_M initial state: moments of the initial fields into a.Mbuf, and (after
 // the solve) f = f*(mu) into the state buffer a.B
 hipError_t launch_init_M_moments(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,

@@ -71,6 +71,7 @@ SIGNATURES = {
     "lbm_ehrenfest_stats": (C.c_int, [_P, C.POINTER(lbm_es_stats), _P, _P, C.c_int64]),
     "lbm_candidates": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
     "lbm_set_timing": (C.c_int, [_P, C.c_int]),
+    "lbm_set_fstar_tolerance": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, C.c_int32]),
     "lbm_kernel_time": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "lbm_layout": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "lbm_struct_sizes": (None, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -242,6 +243,11 @@ class Lattice:
         check(load().lbm_candidates(self.ctx, sites.ctypes.data, ds.ctypes.data, n.value, C.byref(n)),
               "lbm_candidates")
         return sites[:n.value], ds[:n.value]
+
+    def set_fstar_tolerance(self, tol: float = 1e-10, tol32: float = 2e-6, max32: int = 16,
+                            max64: int = 6) -> None:
+        """Residual targets and first-pass update budgets of the f*_M solve."""
+        check(load().lbm_set_fstar_tolerance(self.ctx, tol, tol32, max32, max64), "lbm_set_fstar_tolerance")
 
     def set_timing(self, on: bool) -> None:
         check(load().lbm_set_timing(self.ctx, int(on)), "lbm_set_timing")

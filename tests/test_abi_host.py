@@ -112,3 +112,4 @@ def test_probe_and_spectrum_reject_bad_arguments_without_gpu(L):
     assert lib.lbm_dft_power(None, 4, buf, None, None) == L.LBM_E_INVAL
     assert lib.lbm_dft_power(buf, 0, buf, None, None) == L.LBM_E_INVAL
     assert lib.lbm_dft_power(buf, (1 << 31) + 1, buf, None, None) == L.LBM_E_INVAL
+    assert lib.lbm_set_fstar_tolerance(None, 1e-10, 2e-6, 16, 6) == L.LBM_E_INVAL

@@ -222,6 +222,75 @@ def test_entropic_fstarM_in_step(prec):
     lat.close()
 
 
+@pytest.mark.parametrize("start,prec", [("closed", FP32), ("prev", FP64), ("prev", FP32)])
+def test_entropic_fstarM_step_starts(start, prec):
+    """The closed-form and previous-step starts of the f*_M solve inside the
+    step give the oracle's step (the start changes the iterations only)."""
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    d, rho, u, e0 = _fstarM_case()
+    st0 = lbm.LBM_START_CLOSED_FORM if start == "closed" else lbm.LBM_START_PREV
+    say("case fstarM step start", start, "prec", prec)
+    lat = lattice(d, prec, rho, u, twoE0=e0, fstar_start=st0)
+    f = perturb(lat.get_populations().double().cpu().numpy(), 14, 0.02, d["solid"])
+    lat.set_populations(torch.from_numpy(f))
+    f = lat.get_populations().double().cpu().numpy()
+    tol = 1e-11 if prec == FP64 else 1e-5
+    for s in range(3):
+        g, o, st = compare_step(lat, d, f, tol, label="fstarM %s step %d" % (start, s))
+        assert st.newton_updates > 0 and st.n_fallback == 0
+        f = g
+    lat.close()
+
+
+@pytest.mark.parametrize("budget,target", [((0, 1), 1e-13), ((2, 1), 1e-10)])
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_entropic_fstarM_step_fallback(prec, budget, target):
+    """First-pass budgets too small for the residual target: the sites that
+    miss it (all of them with (0, 1)) are solved by the damped fallback and
+    collided there; the step still matches the oracle.  The fallback stops as
+    soon as the residual is below the target, so its populations are as
+    accurate as that target: with 1e-13 they meet the usual FP64 bound, with
+    the default 1e-10 they agree to 2e-10."""
+    torch = torch_gpu()
+    d, rho, u, e0 = _fstarM_case(nx=200, ny=36)
+    say("case fstarM fallback budget", budget, "target", target, "prec", prec)
+    lat = lattice(d, prec, rho, u, twoE0=e0)
+    lat.set_fstar_tolerance(tol=target, max32=budget[0], max64=budget[1])
+    f = perturb(lat.get_populations().double().cpu().numpy(), 15, 0.02, d["solid"])
+    lat.set_populations(torch.from_numpy(f))
+    f = lat.get_populations().double().cpu().numpy()
+    tol = (1e-11 if target < 1e-12 else 2e-10) if prec == FP64 else 1e-5
+    n_fluid = d["nx"] * d["ny"] - int(np.prod(d["solid"][2:]))
+    for s in range(2):
+        g, o, st = compare_step(lat, d, f, tol, label="fstarM fallback %s step %d" % (budget, s))
+        say("  fallbacks", st.n_fallback, "of", n_fluid)
+        assert st.n_fallback > 0
+        if budget == (0, 1):
+            assert st.n_fallback >= 0.99 * n_fluid
+        f = g
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_elbm_with_fstarM(prec):
+    """ELBM (eq. elbmLB) with the f*_M quasiequilibrium and Ehrenfests' steps
+    on the small cylinder channel."""
+    torch = torch_gpu()
+    d, rho, u, e0 = _fstarM_case()
+    d = dict(d, collision=1)
+    say("case elbm fstarM prec", prec)
+    lat = lattice(d, prec, rho, u, twoE0=e0)
+    f = perturb(lat.get_populations().double().cpu().numpy(), 16, 0.02, d["solid"])
+    lat.set_populations(torch.from_numpy(f))
+    f = lat.get_populations().double().cpu().numpy()
+    tol = 1e-11 if prec == FP64 else 1e-5
+    for s in range(2):
+        g, o, st = compare_step(lat, d, f, tol, label="elbm fstarM step %d" % s)
+        f = g
+    lat.close()
+
+
 def test_entropic_fstarM_network_start_with_fallback():
     """An untrained network start: the warm-started Newton pass misses the
     tolerance at many sites, the plain-Newton fallback re-solves them, and the
