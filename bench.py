@@ -107,6 +107,51 @@ def cylinder_leg(args, torch, lbm, W, net):
     return out
 
 
+def channel_leg(args, torch, lbm, W):
+    """Flow past the square cylinder on 1200 x 400 (side 40 centred at
+    (300, 200), inlet u = (0.05, 0), zero-gradient outlet, free-slip walls,
+    polynomial QE, FP32, delta = 1e-3, k = 64) at Re = 1000, 5000 and 20000,
+    each for the full run length, through the step graphs; the Ehrenfests'
+    statistics (and the FP64 sums behind them) are read every `chunk` steps."""
+    out = {"lattice": "1200x400", "steps": args.channel_steps, "precision": "fp32"}
+    chunk = 1000
+    for re in (1000, 5000, 20000):
+        d, rho, u = W.CONFIGS["cylinder_1200x400_re%d" % re]()
+        cfg = lbm.config_from_workload(d, lbm.LBM_FP32)
+        lat = lbm.Lattice(cfg, rho, u)
+        lat.step(20)
+        torch.cuda.synchronize()
+        print("# channel Re = %d: %d steps" % (re, args.channel_steps), file=sys.stderr, flush=True)
+        above = 0
+        samples = 0
+        t0 = time.perf_counter()
+        done = 0
+        nonfinite_in = None
+        while done < args.channel_steps:
+            n = min(chunk, args.channel_steps - done)
+            lat.step(n)
+            done += n
+            st, _, _ = lat.stats()
+            if st.nonfinite:
+                # the run has diverged somewhere in this chunk: stop it there
+                nonfinite_in = [done - n, done]
+                break
+            above += st.n_above_delta
+            samples += 1
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sites = d["nx"] * d["ny"]
+        r = {"steps_run": done, "MLUPS": round(sites * done / dt / 1e6, 1),
+             "ms_per_step": round(dt * 1e3 / done, 5),
+             "mean_n_above_delta_sampled": round(above / max(samples, 1), 2),
+             "selected_total": st.total_selected, "nonfinite_in_steps": nonfinite_in}
+        if nonfinite_in is None:
+            r["mass"] = st.mass
+        out["re%d" % re] = r
+        lat.close()
+    return out
+
+
 def active_leg(args, torch, lbm, lat, n_sites):
     """The same lattice with an outbreak of non-equilibrium: populations of a
     band of `rows` rows multiplied by 1 + 0.05 xi (xi uniform in [-1, 1),
@@ -230,6 +275,8 @@ def main():
     ap.add_argument("--active-rows", type=int, default=256)
     ap.add_argument("--active-steps", type=int, default=200)
     ap.add_argument("--no-cylinder", action="store_true", help="skip the f*_M cylinder run")
+    ap.add_argument("--no-channel", action="store_true", help="skip the 1200 x 400 cylinder channel runs")
+    ap.add_argument("--channel-steps", type=int, default=50000)
     ap.add_argument("--cyl-steps", type=int, default=2000)
     ap.add_argument("--fx", type=int, default=4096)
     ap.add_argument("--fy", type=int, default=2048)
@@ -333,6 +380,8 @@ def main():
         print("# Ehrenfests' steps at full load", file=sys.stderr, flush=True)
         out["ehrenfest_active"] = active_leg(args, torch, lbm, lat, n_sites)
     lat.close()
+    if not args.no_channel:
+        out["channel_1200x400"] = channel_leg(args, torch, lbm, W)
     if not args.no_fstar:
         print("# f*_M leg", file=sys.stderr, flush=True)
         out["fstar"] = fstar_leg(args, torch, lbm, W)
