@@ -183,8 +183,9 @@ int lbm_candidates(lbm_ctx* ctx, int64_t* sites, double* dS, int64_t cap, int64_
 
 /*
  * f*_M solver of a context (LBM_QE_ENTROPIC_M): residual target tol of the
- * FP64 phase (default 1e-10), target tol32 of the FP32 phase (2e-6) and the
- * update budgets of the first pass (max32 = 16, max64 = 6).  A site that
+ * FP64 phase (default 1e-10 in FP32 contexts, 1e-13 in FP64 contexts),
+ * target tol32 of the FP32 phase (2e-6) and the update budgets of the first
+ * pass (max32 = 16, max64 = 6).  A site that
  * misses tol within the budgets is solved again by the damped FP64 Newton
  * fallback from the rest start (Sec. 3.3's multipliers; counted in
  * lbm_es_stats.n_fallback).  Returns LBM_E_INVAL for another quasiequilibrium

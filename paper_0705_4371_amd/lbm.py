@@ -244,9 +244,12 @@ class Lattice:
               "lbm_candidates")
         return sites[:n.value], ds[:n.value]
 
-    def set_fstar_tolerance(self, tol: float = 1e-10, tol32: float = 2e-6, max32: int = 16,
+    def set_fstar_tolerance(self, tol: float = None, tol32: float = 2e-6, max32: int = 16,
                             max64: int = 6) -> None:
-        """Residual targets and first-pass update budgets of the f*_M solve."""
+        """Residual targets and first-pass update budgets of the f*_M solve
+        (tol defaults to the context's own: 1e-10 FP32, 1e-13 FP64)."""
+        if tol is None:
+            tol = 1e-13 if self.cfg.precision == LBM_FP64 else 1e-10
         check(load().lbm_set_fstar_tolerance(self.ctx, tol, tol32, max32, max64), "lbm_set_fstar_tolerance")
 
     def set_timing(self, on: bool) -> None:

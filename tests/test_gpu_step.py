@@ -251,7 +251,7 @@ def test_entropic_fstarM_step_fallback(prec, budget, target):
     collided there; the step still matches the oracle.  The fallback stops as
     soon as the residual is below the target, so its populations are as
     accurate as that target: with 1e-13 they meet the usual FP64 bound, with
-    the default 1e-10 they agree to 2e-10."""
+    1e-10 (the FP32 contexts' default) they agree to 2e-10."""
     torch = torch_gpu()
     d, rho, u, e0 = _fstarM_case(nx=200, ny=36)
     say("case fstarM fallback budget", budget, "target", target, "prec", prec)
