@@ -350,7 +350,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
     ALLOC(c->mubuf, sizeof(double) * 4 * ncap);
     ALLOC(c->fctr, 16);
     ALLOC(c->fail_list, sizeof(uint32_t) * ncap);
-    ALLOC(c->fstats, sizeof(FstarStats));
+    ALLOC(c->fstats, sizeof(FstarStats) * FSTAR_STAT_SLOTS);
     if (cfg->fstar_start == LBM_START_MLP) ALLOC(c->warm, sizeof(float) * 4 * ncap);
     FstarArgs& f = c->fa;
     f.M = c->Mbuf;
@@ -544,8 +544,9 @@ int lbm_ehrenfest_stats(lbm_ctx* c, lbm_es_stats* out, int64_t* sel, double* sel
   out->n_fallback = 0;
   out->newton_updates = 0;
   if (c->cfg.qe == LBM_QE_ENTROPIC_M) {
-    FstarStats fs;
-    HIPCHK(hipMemcpy(&fs, c->fstats, sizeof(fs), hipMemcpyDeviceToHost));
+    FstarStats slots[FSTAR_STAT_SLOTS];
+    HIPCHK(hipMemcpy(slots, c->fstats, sizeof(slots), hipMemcpyDeviceToHost));
+    const FstarStats fs = fstar_stats_total(slots);
     out->n_fallback = (int64_t)(fs.fallback + fs.infeasible);
     out->newton_updates = (int64_t)(fs.sum32 + fs.sum64);
   }

@@ -54,7 +54,7 @@ int lbm_fstar_create(int64_t max_n, void* stream, lbm_fstar** out) {
   bool ok = hipMalloc((void**)&s->ctr, 16) == hipSuccess &&
             hipMalloc((void**)&s->fail_list, sizeof(uint32_t) * (size_t)max_n) == hipSuccess &&
             hipMalloc((void**)&s->warm, sizeof(float) * 4 * (size_t)max_n) == hipSuccess &&
-            hipMalloc((void**)&s->stats, sizeof(FstarStats)) == hipSuccess;
+            hipMalloc((void**)&s->stats, sizeof(FstarStats) * FSTAR_STAT_SLOTS) == hipSuccess;
   if (!ok) {
     lbm_fstar_free(s);
     return lbm_internal_fail(LBM_E_NOMEM, "solver workspace allocation failed");
@@ -115,9 +115,10 @@ int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_
   }
   HIPCHK(launch_fstar(a, kind, s->stream));
   if (st) {
-    FstarStats h;
-    HIPCHK(hipMemcpyAsync(&h, s->stats, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    FstarStats slots[FSTAR_STAT_SLOTS];
+    HIPCHK(hipMemcpyAsync(slots, s->stats, sizeof(slots), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    const FstarStats h = fstar_stats_total(slots);
     std::memset(st, 0, sizeof(*st));
     st->n = n;
     st->n_infeasible = (int64_t)h.infeasible;

@@ -68,21 +68,21 @@ __global__ __launch_bounds__(64) void k_fstar_fallback(FstarArgs a) {
     const int it = newton64_damped(u1, u2, e, a.tol, 200, s, res);
     write_mu(a, i, rho, s);
     if (a.status) a.status[i] = it >= 0 ? 1 : 3;
-    atomicAdd(&a.stats->fallback, 1ull);
-    if (it < 0) atomicAdd(&a.stats->failed, 1ull);
-    else atomicMax(&a.stats->maxres_bits, (unsigned long long)__double_as_longlong(res));
+    FstarStats& S = stat_slot(a.stats);
+    atomicAdd(&S.fallback, 1ull);
+    if (it < 0) atomicAdd(&S.failed, 1ull);
+    else atomicMax(&S.maxres_bits, (unsigned long long)__double_as_longlong(res));
   }
 }
 
+// zeroes the failure counter and every copy of the statistics (all of their
+// fields are 64-bit words)
 __global__ void k_fstar_clear(FstarArgs a) {
   const int t = threadIdx.x;
   if (t < 4) a.ctr[t] = 0;
-  if (t < 16) a.stats->hist[t] = 0;
-  if (t == 0) {
-    a.stats->sum32 = a.stats->sum64 = a.stats->infeasible = 0;
-    a.stats->fallback = a.stats->failed = 0;
-    a.stats->maxres_bits = 0;
-  }
+  unsigned long long* w = (unsigned long long*)a.stats;
+  constexpr int words = FSTAR_STAT_SLOTS * (int)(sizeof(FstarStats) / 8);
+  for (int j = t; j < words; j += 64) w[j] = 0ull;
 }
 
 hipError_t launch_fstar_clear(const FstarArgs& a, hipStream_t s) {

@@ -15,6 +15,33 @@ struct FstarStats {
   unsigned long long maxres_bits; // bits of the largest final residual (non-negative double)
 };
 
+// The device keeps FSTAR_STAT_SLOTS copies of the statistics; a workgroup
+// adds into copy blockIdx mod FSTAR_STAT_SLOTS, so that the per-workgroup
+// atomics of a solve are spread over that many addresses instead of
+// serialising on one (measured: with one copy, each extra workgroup of the
+// time step's solve cost about 44 ns).  Readers sum the copies.
+constexpr int FSTAR_STAT_SLOTS = 16;
+
+__device__ __forceinline__ FstarStats& stat_slot(FstarStats* s) {
+  return s[blockIdx.x & (FSTAR_STAT_SLOTS - 1)];
+}
+
+// sum (max for the residual) of the copies, on the host
+inline FstarStats fstar_stats_total(const FstarStats* slots) {
+  FstarStats t = slots[0];
+  for (int k = 1; k < FSTAR_STAT_SLOTS; ++k) {
+    const FstarStats& s = slots[k];
+    for (int i = 0; i < 16; ++i) t.hist[i] += s.hist[i];
+    t.sum32 += s.sum32;
+    t.sum64 += s.sum64;
+    t.infeasible += s.infeasible;
+    t.fallback += s.fallback;
+    t.failed += s.failed;
+    if (s.maxres_bits > t.maxres_bits) t.maxres_bits = s.maxres_bits;
+  }
+  return t;
+}
+
 struct FstarArgs {
   const double* M;      // [4][n]
   int64_t n;
@@ -26,7 +53,7 @@ struct FstarArgs {
   uint8_t* status;      // [n] or null: 0 ok, 1 fallback ok, 2 infeasible, 3 failed
   uint32_t* ctr;        // [4]: ctr[0] = number of failures of the first pass
   uint32_t* fail_list;  // [n]
-  FstarStats* stats;
+  FstarStats* stats;    // [FSTAR_STAT_SLOTS]
   double tol;           // FP64 residual target
   float tol32;          // FP32 phase target
   int max32, max64;     // iteration budgets of the two phases

@@ -211,7 +211,8 @@ __device__ __forceinline__ void solve_hist(SolveAcc& sh, bool live, int updates)
 }
 
 // wavefront reductions of the per-thread statistics, one LDS atomic per
-// wavefront, then one global atomic per counter and workgroup
+// wavefront, then one global atomic per counter and workgroup (into the
+// workgroup's copy of the statistics)
 __device__ __forceinline__ void solve_flush(const FstarArgs& a, SolveAcc& sh, uint32_t sum32, uint32_t sum64,
                                             uint32_t ninf, double maxres) {
   const int lane = threadIdx.x & 63;
@@ -229,12 +230,13 @@ __device__ __forceinline__ void solve_flush(const FstarArgs& a, SolveAcc& sh, ui
     atomicMax(&sh.maxres_bits, (unsigned long long)__double_as_longlong(maxres));
   }
   __syncthreads();
-  if (threadIdx.x < 16 && sh.hist[threadIdx.x]) atomicAdd(&a.stats->hist[threadIdx.x], (unsigned long long)sh.hist[threadIdx.x]);
+  FstarStats& S = stat_slot(a.stats);
+  if (threadIdx.x < 16 && sh.hist[threadIdx.x]) atomicAdd(&S.hist[threadIdx.x], (unsigned long long)sh.hist[threadIdx.x]);
   if (threadIdx.x == 16) {
-    atomicAdd(&a.stats->sum32, (unsigned long long)sh.sum32);
-    atomicAdd(&a.stats->sum64, (unsigned long long)sh.sum64);
-    atomicAdd(&a.stats->infeasible, (unsigned long long)sh.infeasible);
-    atomicMax(&a.stats->maxres_bits, sh.maxres_bits);
+    atomicAdd(&S.sum32, (unsigned long long)sh.sum32);
+    atomicAdd(&S.sum64, (unsigned long long)sh.sum64);
+    atomicAdd(&S.infeasible, (unsigned long long)sh.infeasible);
+    atomicMax(&S.maxres_bits, sh.maxres_bits);
   }
 }
 

@@ -1081,9 +1081,10 @@ __global__ __launch_bounds__(64) void k_fstep_fallback(StepArgs s, FstarArgs a) 
     const int it = newton64_damped(u1, u2, e, a.tol, 200, q, res);
     write_mu(a, i, rho, q);
     if (a.status) a.status[i] = it >= 0 ? 1 : 3;
-    atomicAdd(&a.stats->fallback, 1ull);
-    if (it < 0) atomicAdd(&a.stats->failed, 1ull);
-    else atomicMax(&a.stats->maxres_bits, (unsigned long long)__double_as_longlong(res));
+    FstarStats& S = stat_slot(a.stats);
+    atomicAdd(&S.fallback, 1ull);
+    if (it < 0) atomicAdd(&S.failed, 1ull);
+    else atomicMax(&S.maxres_bits, (unsigned long long)__double_as_longlong(res));
 
     const int64_t y = i / g.nx, x = i - y * g.nx;
     T f[9], fs[9];
