@@ -273,8 +273,9 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
 // Key of a candidate: the 63 bits of its non-negative FP64 Delta S followed
 // by the 32 bits of ~site (a larger key = larger Delta S, then lower site).
 // Keys are unique, so "the k largest keys" is one well-defined set.
-//   k_rank      FP64 Delta S of the screened sites; candidates are appended
-//               with one atomic per workgroup; when more than k sites were
+//   k_rank      FP64 Delta S of the screened sites; candidates are collected
+//               per workgroup in LDS and appended with one atomic per flush
+//               of that buffer; when more than k sites were
 //               screened, a 2^15-bin histogram of the top key bits is built
 //               (in LDS per workgroup when many sites are screened).
 //   k_partition with more than k candidates, each workgroup finds the bin b*
@@ -350,10 +351,19 @@ __device__ __forceinline__ double rank_site(const StepArgs& a, const T* __restri
 constexpr int RANK_BLOCKS = 512;
 constexpr uint32_t LDS_HIST_MIN = 16384;  // screened sites above which the histogram is built in LDS
 
+// The candidates of a workgroup are collected in LDS and written out with
+// one global atomic per flush (when more than RANK_BUF - 256 are buffered,
+// and at the end): every workgroup appends to the same counter, where
+// atomics serialise (about 40 ns each here), so that an outbreak would
+// otherwise queue on it.  With the 64 KB histogram the workgroup stays
+// within half of the 160 KB of LDS, so two workgroups fit on a CU.
+constexpr uint32_t RANK_BUF = 1000;
+
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
   __shared__ uint32_t s_hist[HIST_BINS / 2];  // two 16-bit counts per word
-  __shared__ uint32_t s_cnt[4], s_base, s_inv[4];
+  __shared__ Cand s_cand[RANK_BUF];
+  __shared__ uint32_t s_cnt[4], s_base, s_inv[4], s_nc, s_gbase;
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -364,10 +374,10 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
   const bool lds = need_hist && n > LDS_HIST_MIN;
   // only the workgroups that hold screened sites take part
   if (blockIdx.x * 256u >= n) return;
-  if (lds) {
+  if (lds)
     for (int j = tid; j < HIST_BINS / 2; j += 256) s_hist[j] = 0u;
-    __syncthreads();
-  }
+  if (tid == 0) s_nc = 0u;
+  __syncthreads();
   uint32_t it = 0;
   // the trip count is uniform over the workgroup (block barriers inside)
   for (uint32_t t0 = blockIdx.x * 256u; t0 < n; t0 += gridDim.x * 256u) {
@@ -380,28 +390,49 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
       ds = rank_site<T, Q, QE, PULL>(a, A, g, site);
       is_c = ds > g.delta;
     }
-    const uint32_t slot = block_append(is_c, &a.ctr[C_CAND], s_cnt, &s_base);
-    const uint32_t bin = ds_bin(ds);
-    const unsigned long long inv = __ballot(is_c && __builtin_isinf(ds));
+    // slot in the workgroup's buffer (s_nc is advanced by thread 0 only)
+    const unsigned long long cm = __ballot(is_c);
+    if (lane == 0) s_cnt[w] = (uint32_t)__popcll(cm);
+    const bool inv_c = is_c && __builtin_isinf(ds);
+    const unsigned long long inv = __ballot(inv_c);
     if (lane == 0) s_inv[w] = (uint32_t)__popcll(inv);
+    __syncthreads();
+    uint32_t lslot = s_nc;
+    for (int v = 0; v < w; ++v) lslot += s_cnt[v];
+    lslot += (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
+    if (is_c) s_cand[lslot] = Cand{site, 0u, ds};
+    const uint32_t bin = ds_bin(ds);
     if (lds) {
       if (is_c) atomicAdd(&s_hist[bin >> 1], 1u << (16 * (bin & 1u)));
     } else if (need_hist) {
       // global histogram: lanes that share the wave leader's bin are merged
-      const unsigned long long mask = __ballot(is_c);
-      if (mask) {
-        const int leader = __ffsll((long long)mask) - 1;
+      if (cm) {
+        const int leader = __ffsll((long long)cm) - 1;
         const uint32_t lbin = (uint32_t)__shfl((int)bin, leader);
         const unsigned long long same = __ballot(is_c && bin == lbin);
         if (is_c && bin != lbin) atomicAdd(&a.hist[bin], 1u);
         if (lane == leader) atomicAdd(&a.hist[lbin], (uint32_t)__popcll(same));
       }
     }
-    if (is_c) a.cand[slot] = Cand{site, 0u, ds};
     __syncthreads();
     if (tid == 0) {
+      s_nc += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
       const uint32_t ni = s_inv[0] + s_inv[1] + s_inv[2] + s_inv[3];
       if (ni) atomicAdd(&a.ctr[C_INVALID], ni);
+    }
+    __syncthreads();
+    // flush the buffer before it can overflow (at most 256 more per
+    // iteration) and after the last iteration
+    const bool last = t0 + gridDim.x * 256u >= n;
+    const uint32_t nb = s_nc;
+    if (nb > RANK_BUF - 256u || (last && nb > 0u)) {
+      if (tid == 0) s_gbase = atomicAdd(&a.ctr[C_CAND], nb);
+      __syncthreads();
+      const uint32_t gb = s_gbase;
+      for (uint32_t j = tid; j < nb; j += 256u) a.cand[gb + j] = s_cand[j];
+      __syncthreads();
+      if (tid == 0) s_nc = 0u;
+      __syncthreads();
     }
     // flushed every 128 iterations: at most 128 x 256 = 32768 keys per
     // 16-bit count
