@@ -515,8 +515,9 @@ __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
     const bool bnd = t < nc && !all && k > 0 && bin == bstar;
     if (t < nc) mx = ds_bits(c.ds) > mx ? ds_bits(c.ds) : mx;
     if (take) mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
-    const uint32_t s1 = block_append(take, &a.ctr[C_NSEL0], s_cnt, &s_base);
-    const uint32_t s2 = block_append(bnd, &a.ctr[C_NBND], s_cnt, &s_base);
+    // most iterations have nothing to append: one barrier decides it
+    const uint32_t s1 = __syncthreads_or(take) ? block_append(take, &a.ctr[C_NSEL0], s_cnt, &s_base) : 0u;
+    const uint32_t s2 = __syncthreads_or(bnd) ? block_append(bnd, &a.ctr[C_NBND], s_cnt, &s_base) : 0u;
     if (take) {
       a.sel[s1] = c.site;
       a.sel_ds[s1] = c.ds;
@@ -547,11 +548,16 @@ __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
 
 // k_refine: the boundary refinement, the statistics and the clearing of the
 // counters for the next step, by one workgroup of 256 threads
+// boundary keys staged in LDS by k_refine (more are read from memory)
+constexpr uint32_t REFINE_LDS = 8192;
+
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
   __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_nsel, s_dig, s_rr, s_exact;
   __shared__ unsigned long long s_mn[4];
+  __shared__ unsigned long long s_khi[REFINE_LDS];
+  __shared__ uint32_t s_klo[REFINE_LDS];
   const int tid = threadIdx.x;
   const uint32_t nc = a.ctr[C_CAND];
   const uint32_t n = a.ctr[C_SCREEN];
@@ -564,6 +570,17 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
   __syncthreads();
 
   if (nc > 0 && !all) {
+    // the remaining key of each boundary candidate: Delta S bits 47..0 and
+    // ~site, read once from memory into LDS when they fit
+    const bool staged = m <= REFINE_LDS;
+    if (staged) {
+      for (uint32_t t = tid; t < m; t += 256) {
+        const Cand c = a.bnd[t];
+        s_khi[t] = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
+        s_klo[t] = ~c.site;
+      }
+      __syncthreads();
+    }
     // 8-bit digits of the remaining key below the histogram bits: Delta S
     // bits 47..0, then ~site; rr keys are still to be taken
     unsigned long long Thi = 0, Mhi = 0;
@@ -574,9 +591,16 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
       s_hist[tid] = 0;
       __syncthreads();
       for (uint32_t t = tid; t < m; t += 256) {
-        const Cand c = a.bnd[t];
-        const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
-        const uint32_t lo = ~c.site;
+        unsigned long long hi;
+        uint32_t lo;
+        if (staged) {
+          hi = s_khi[t];
+          lo = s_klo[t];
+        } else {
+          const Cand c = a.bnd[t];
+          hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
+          lo = ~c.site;
+        }
         if ((hi & Mhi) == Thi && (lo & Mlo) == Tlo) {
           const uint32_t d = inhi ? (uint32_t)(hi >> sh) & 255u : (lo >> sh) & 255u;
           atomicAdd(&s_hist[d], 1u);
