@@ -678,7 +678,9 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
   }
 }
 
-constexpr int PART_BLOCKS = 256;
+// 1024 workgroups: 4% faster than 256 on a step with 1.3 million
+// candidates (each workgroup first locates b* in the histogram itself)
+constexpr int PART_BLOCKS = 1024;
 
 // ---------------------------------------------------------------------------
 // k_select_one: the whole ranking and selection in one workgroup of 512
