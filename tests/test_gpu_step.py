@@ -272,6 +272,63 @@ def test_entropic_fstarM_step_fallback(prec, budget, target):
     lat.close()
 
 
+@pytest.mark.parametrize("start", ["rest", "prev"])
+def test_fstarM_graph_replay_matches_direct_launches(start):
+    """The fused f*_M step (solve, collision, fallback and the statistics
+    clear inside the captured graphs): three rounds of 32 graph-replayed
+    steps, each checked bit for bit against as many directly launched steps
+    after the host has read the state back, then one step against the
+    oracle."""
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    d, rho, u, e0 = _fstarM_case(nx=200, ny=36)
+    st0 = lbm.LBM_START_DEFAULT if start == "rest" else lbm.LBM_START_PREV
+    say("case fstarM graph replay start", start)
+    a = lattice(d, FP32, rho, u, twoE0=e0, fstar_start=st0)
+    b = lattice(d, FP32, rho, u, twoE0=e0, fstar_start=st0)
+    f0 = perturb(a.get_populations().double().cpu().numpy(), 18, 0.02, d["solid"])
+    a.set_populations(torch.from_numpy(f0))
+    b.set_populations(torch.from_numpy(f0))
+    a.step(1)                    # the first step after set_populations is direct in both
+    b.step(1)
+    b.set_timing(True)           # timing mode launches kernels directly
+    for r in range(3):
+        a.step(32)
+        b.step(32)
+        ga = a.get_populations().cpu().numpy()
+        gb = b.get_populations().cpu().numpy()
+        assert np.array_equal(ga, gb), "replay round %d" % r
+        sa, _, _ = a.stats()
+        sb, _, _ = b.stats()
+        assert (sa.total_selected, sa.newton_updates, sa.n_fallback) == \
+            (sb.total_selected, sb.newton_updates, sb.n_fallback), "replay round %d" % r
+        say("  round", r, "selected", sa.total_selected, "updates", sa.newton_updates)
+    f = a.get_populations().double().cpu().numpy()
+    compare_step(a, d, f, 1e-5, label="fstarM after graphs")
+    a.close()
+    b.close()
+
+
+def test_elbm_fstarM_fallback_fp64():
+    """ELBM with the f*_M quasiequilibrium and every site forced through the
+    damped fallback, whose collision then takes the ELBM alpha."""
+    torch = torch_gpu()
+    d, rho, u, e0 = _fstarM_case(nx=200, ny=36)
+    d = dict(d, collision=1)
+    say("case elbm fstarM fallback")
+    lat = lattice(d, FP64, rho, u, twoE0=e0)
+    lat.set_fstar_tolerance(tol=1e-13, max32=0, max64=1)
+    f = perturb(lat.get_populations().double().cpu().numpy(), 19, 0.02, d["solid"])
+    lat.set_populations(torch.from_numpy(f))
+    f = lat.get_populations().double().cpu().numpy()
+    n_fluid = d["nx"] * d["ny"] - int(np.prod(d["solid"][2:]))
+    for s in range(2):
+        g, o, st = compare_step(lat, d, f, 1e-11, label="elbm fstarM fallback step %d" % s)
+        assert st.n_fallback >= 0.99 * n_fluid
+        f = g
+    lat.close()
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_elbm_with_fstarM(prec):
     """ELBM (eq. elbmLB) with the f*_M quasiequilibrium and Ehrenfests' steps
