@@ -288,8 +288,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the lattice would be split into y-slabs with halo exchange; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the lattice would be split into y-slabs of whole rows with a one-row halo exchange "
+              "and an all-gather of the local top-k keys)",
               file=sys.stderr)
         sys.exit(2)
 
