@@ -553,7 +553,7 @@ constexpr uint32_t REFINE_LDS = 8192;
 
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
-  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_hist[256], s_scan[256];
   __shared__ uint32_t s_nsel, s_dig, s_rr, s_exact;
   __shared__ unsigned long long s_mn[4];
   __shared__ unsigned long long s_khi[REFINE_LDS];
@@ -607,13 +607,20 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
         }
       }
       __syncthreads();
-      if (tid == 0) {
-        uint32_t c = 0;
-        for (int d = 255; d >= 0; --d) {
-          const uint32_t h = s_hist[d];
-          if (c + h >= rr) { s_dig = (uint32_t)d; s_rr = rr - c; s_exact = (h == rr - c); break; }
-          c += h;
-        }
+      // the digit holding the rr-th largest remaining key: suffix sums of the
+      // counts from digit 255 down (thread t holds digit 255 - t), one LDS
+      // scan instead of a serial walk by one thread
+      s_scan[tid] = s_hist[255 - tid];
+      __syncthreads();
+      for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
+        __syncthreads();
+        s_scan[tid] += v;
+        __syncthreads();
+      }
+      {
+        const uint32_t incl = s_scan[tid], h = s_hist[255 - tid], excl = incl - h;
+        if (excl < rr && incl >= rr) { s_dig = 255u - (uint32_t)tid; s_rr = rr - excl; s_exact = (h == rr - excl); }
       }
       __syncthreads();
       const uint32_t d = s_dig;
