@@ -352,18 +352,22 @@ constexpr int RANK_BLOCKS = 512;
 constexpr uint32_t LDS_HIST_MIN = 16384;  // screened sites above which the histogram is built in LDS
 
 // The candidates of a workgroup are collected in LDS and written out with
-// one global atomic per flush (when more than RANK_BUF - 256 are buffered,
+// one global atomic per flush (when more than RANK_BUF - RANK_TX are buffered,
 // and at the end): every workgroup appends to the same counter, where
 // atomics serialise (about 40 ns each here), so that an outbreak would
 // otherwise queue on it.  With the 64 KB histogram the workgroup stays
 // within half of the 160 KB of LDS, so two workgroups fit on a CU.
 constexpr uint32_t RANK_BUF = 1000;
+// 512 lanes per workgroup: the LDS above (about 80 KB) then serves 16 waves
+// of a CU (two workgroups) instead of 8 -- the ranking is latency bound
+constexpr uint32_t RANK_TX = 512;
+constexpr int RANK_W = RANK_TX / 64;
 
 template <typename T, int Q, int QE, bool PULL>
-__global__ __launch_bounds__(256) void k_rank(StepArgs a) {
+__device__ __forceinline__ void rank_body(const StepArgs& a) {
   __shared__ uint32_t s_hist[HIST_BINS / 2];  // two 16-bit counts per word
   __shared__ Cand s_cand[RANK_BUF];
-  __shared__ uint32_t s_cnt[4], s_base, s_inv[4], s_nc, s_gbase;
+  __shared__ uint32_t s_cnt[RANK_W], s_inv[RANK_W], s_nc, s_gbase;
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -373,14 +377,14 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
   const bool need_hist = k > 0 && n > k;
   const bool lds = need_hist && n > LDS_HIST_MIN;
   // only the workgroups that hold screened sites take part
-  if (blockIdx.x * 256u >= n) return;
+  if (blockIdx.x * RANK_TX >= n) return;
   if (lds)
-    for (int j = tid; j < HIST_BINS / 2; j += 256) s_hist[j] = 0u;
+    for (int j = tid; j < HIST_BINS / 2; j += (int)RANK_TX) s_hist[j] = 0u;
   if (tid == 0) s_nc = 0u;
   __syncthreads();
   uint32_t it = 0;
   // the trip count is uniform over the workgroup (block barriers inside)
-  for (uint32_t t0 = blockIdx.x * 256u; t0 < n; t0 += gridDim.x * 256u) {
+  for (uint32_t t0 = blockIdx.x * RANK_TX; t0 < n; t0 += gridDim.x * RANK_TX) {
     const uint32_t t = t0 + tid;
     bool is_c = false;
     double ds = 0.0;
@@ -416,29 +420,30 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-      s_nc += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-      const uint32_t ni = s_inv[0] + s_inv[1] + s_inv[2] + s_inv[3];
+      uint32_t nn = 0, ni = 0;
+      for (int v = 0; v < RANK_W; ++v) { nn += s_cnt[v]; ni += s_inv[v]; }
+      s_nc += nn;
       if (ni) atomicAdd(&a.ctr[C_INVALID], ni);
     }
     __syncthreads();
-    // flush the buffer before it can overflow (at most 256 more per
+    // flush the buffer before it can overflow (at most RANK_TX more per
     // iteration) and after the last iteration
-    const bool last = t0 + gridDim.x * 256u >= n;
+    const bool last = t0 + gridDim.x * RANK_TX >= n;
     const uint32_t nb = s_nc;
-    if (nb > RANK_BUF - 256u || (last && nb > 0u)) {
+    if (nb > RANK_BUF - RANK_TX || (last && nb > 0u)) {
       if (tid == 0) s_gbase = atomicAdd(&a.ctr[C_CAND], nb);
       __syncthreads();
       const uint32_t gb = s_gbase;
-      for (uint32_t j = tid; j < nb; j += 256u) a.cand[gb + j] = s_cand[j];
+      for (uint32_t j = tid; j < nb; j += RANK_TX) a.cand[gb + j] = s_cand[j];
       __syncthreads();
       if (tid == 0) s_nc = 0u;
       __syncthreads();
     }
-    // flushed every 128 iterations: at most 128 x 256 = 32768 keys per
+    // flushed every 64 iterations: at most 64 x 512 = 32768 keys per
     // 16-bit count
-    if (lds && (++it & 127u) == 0u) {
+    if (lds && (++it & (32768u / RANK_TX - 1u)) == 0u) {
       __syncthreads();
-      for (int j = tid; j < HIST_BINS / 2; j += 256) {
+      for (int j = tid; j < HIST_BINS / 2; j += (int)RANK_TX) {
         const uint32_t v = s_hist[j];
         if (v & 0xFFFFu) atomicAdd(&a.hist[2 * j], v & 0xFFFFu);
         if (v >> 16) atomicAdd(&a.hist[2 * j + 1], v >> 16);
@@ -449,12 +454,25 @@ __global__ __launch_bounds__(256) void k_rank(StepArgs a) {
   }
   if (lds) {
     __syncthreads();
-    for (int j = tid; j < HIST_BINS / 2; j += 256) {
+    for (int j = tid; j < HIST_BINS / 2; j += (int)RANK_TX) {
       const uint32_t v = s_hist[j];
       if (v & 0xFFFFu) atomicAdd(&a.hist[2 * j], v & 0xFFFFu);
       if (v >> 16) atomicAdd(&a.hist[2 * j + 1], v >> 16);
     }
   }
+}
+
+// Two entry points over the same body: at most 128 VGPRs (two workgroups,
+// 16 waves, per CU) where that needs no scratch, and the unconstrained
+// bound for the f*_M quasiequilibrium, whose Delta S would spill within 128.
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(RANK_TX, 4) void k_rank(StepArgs a) {
+  rank_body<T, Q, QE, PULL>(a);
+}
+
+template <typename T, int Q, int QE, bool PULL>
+__global__ __launch_bounds__(RANK_TX) void k_rank_m(StepArgs a) {
+  rank_body<T, Q, QE, PULL>(a);
 }
 
 // b*, the histogram bin that holds the k-th largest key, and r, the keys to
@@ -1204,7 +1222,10 @@ static void select_t(const StepArgs& a, hipStream_t s) {
   if (a.g.ds_on && a.one_wg) {
     hipLaunchKernelGGL((k_select_one<T, Q, QE, PULL>), dim3(1), dim3(ONE_TX), 0, s, a);
   } else if (a.g.ds_on) {
-    hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(256), 0, s, a);
+    if constexpr (QE == QE_ENTROPIC_M)
+      hipLaunchKernelGGL((k_rank_m<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(RANK_TX), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(RANK_TX), 0, s, a);
     hipLaunchKernelGGL((k_partition<T, Q, QE, PULL>), dim3(PART_BLOCKS), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(256), 0, s, a);
   }
