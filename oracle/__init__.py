@@ -4,9 +4,9 @@ start of its entropic quasiequilibrium solve.
 
 TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` import this package.  It shares no code with
-the GPU library ``paper_0705_4371_amd``; the arithmetic lives in
-``oracle.c`` (plain C, FP64, long double for Delta S), this module only
-marshals numpy arrays.
+the GPU library ``paper_0705_4371_amd``; all of its arithmetic lives in
+``oracle.c`` (plain C, FP64, long double for Delta S); this module only
+marshals numpy arrays and composes those functions.
 
 Every function names the passage of the paper it follows in ``oracle.c``.
 Functions without an independent pin are listed as "parity unpinned" in the
@@ -62,6 +62,7 @@ _lib = None
 _D = C.POINTER(C.c_double)
 _I64 = C.POINTER(C.c_int64)
 _I32 = C.POINTER(C.c_int32)
+_F32 = C.POINTER(C.c_float)
 
 
 def lib():
@@ -77,6 +78,8 @@ def lib():
         L.or_fstar_feasible.argtypes = [_D]
         L.or_fstar_newton.argtypes = [_D, C.c_double, C.c_int, _D, _D]
         L.or_fstar_scalar.argtypes = [_D, _D]
+        L.or_fstar_polish.argtypes = [_D, _D]
+        L.or_fstar_polish.restype = C.c_double
         L.or_fstar_from_mu.argtypes = [_D, _D]
         L.or_dft_power.argtypes = [_D, C.c_int64, _D]
         L.or_dft_power.restype = None
@@ -93,6 +96,8 @@ def lib():
         L.or_step_sites.argtypes = [C.POINTER(_Cfg), _D, _I64, C.c_int64, _I64, C.c_int64, _D]
         L.or_site_dS.argtypes = [C.POINTER(_Cfg), _D, C.c_int64]
         L.or_site_dS.restype = C.c_double
+        L.or_sums.argtypes = [C.POINTER(_Cfg), _D, _D]
+        L.or_sums.restype = None
         L.or_mlp_forward.argtypes = [_D, _D, C.c_int64, _D, C.c_int]
         L.or_mlp_forward.restype = C.c_double
         L.or_mlp_loss_grad.argtypes = [_D, _D, _D, C.c_int64, _D, C.c_int]
@@ -101,6 +106,12 @@ def lib():
                                    C.c_double, C.c_double]
         L.or_bf16_round.argtypes = [C.c_double]
         L.or_bf16_round.restype = C.c_double
+        L.or_mlp_features.argtypes = [_D, C.c_int64, _F32, _D]
+        L.or_mlp_features.restype = None
+        L.or_mlp_targets.argtypes = [_D, _D, C.c_int64, _F32, _D]
+        L.or_mlp_targets.restype = None
+        L.or_mlp_unnormalise.argtypes = [_D, C.c_int64, _F32, _D]
+        L.or_mlp_unnormalise.restype = None
         _lib = L
     return _lib
 
@@ -152,6 +163,15 @@ def fstar_newton(M, tol: float = 1e-13, max_iter: int = 100):
     r = np.zeros(1)
     it = lib().or_fstar_newton(_p(M), tol, max_iter, _p(mu), _p(r))
     return mu, int(it), float(r[0])
+
+
+def fstar_polish(M, mu):
+    """One more Newton update of converged multipliers (or_fstar_polish).
+    Returns (mu, residual)."""
+    M = np.ascontiguousarray(M, np.float64)
+    mu = np.array(mu, np.float64)
+    r = lib().or_fstar_polish(_p(M), _p(mu))
+    return mu, float(r)
 
 
 def fstar_scalar(M):
@@ -257,6 +277,16 @@ def site_dS(cfg: _Cfg, f_in: np.ndarray, sites) -> np.ndarray:
     return np.array([lib().or_site_dS(C.byref(cfg), _p(f_in), int(s)) for s in np.asarray(sites).reshape(-1)])
 
 
+def sums(cfg: _Cfg, f: np.ndarray) -> np.ndarray:
+    """Sums over the fluid sites of rho, rho u1, rho u2, 2E of a state f
+    [Q][ny][nx] (or_sums: long double accumulation)."""
+    f = np.ascontiguousarray(f, np.float64)
+    assert f.shape == (cfg.Q, cfg.ny, cfg.nx)
+    out = np.zeros(4)
+    lib().or_sums(C.byref(cfg), _p(f), _p(out))
+    return out
+
+
 def dft_power(x) -> np.ndarray:
     """|DFT|^2 of a real signal at bins 0..n/2, by the definition (or_dft_power);
     the shedding frequency of Sec. 4.2 is the dominant bin of the last quarter
@@ -315,30 +345,49 @@ def adam_step(p, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 # Learned warm start of the f*_M solve: features, targets, network start
 # ---------------------------------------------------------------------------
 
+def _norm(norm16) -> np.ndarray:
+    nm = np.ascontiguousarray(np.asarray(norm16, np.float32).reshape(16))
+    return nm
+
+
 def mlp_features(M, norm16) -> np.ndarray:
-    """Normalised network inputs of moment vectors M [4][n]: the features
-    (u1, u2, 2E/rho, |u|^2) shifted and scaled by norm16[0:4], norm16[4:8];
-    rounded to FP32 as the network receives them."""
-    M = np.asarray(M, np.float64)
-    nm = np.asarray(norm16, np.float32).astype(np.float64)
-    u1, u2, e = M[1] / M[0], M[2] / M[0], M[3] / M[0]
-    feat = np.stack([u1, u2, e, u1 * u1 + u2 * u2], axis=1)
-    return ((feat - nm[0:4]) * nm[4:8]).astype(np.float32).astype(np.float64)
+    """Normalised network inputs [n][4] of moment vectors M [4][n]
+    (or_mlp_features: (u1, u2, 2E/rho, |u|^2), shifted and scaled by
+    norm16[0:4], norm16[4:8], rounded to FP32)."""
+    M = np.ascontiguousarray(M, np.float64)
+    n = M.shape[1]
+    nm = _norm(norm16)
+    X = np.zeros((n, 4))
+    lib().or_mlp_features(_p(M), n, nm.ctypes.data_as(_F32), _p(X))
+    return X
 
 
 def mlp_targets(M, mu, norm16) -> np.ndarray:
-    """Normalised network targets of multipliers mu [4][n]:
-    (mu0 - ln rho, mu1, mu2, mu3) shifted and scaled by norm16[8:12], [12:16]."""
-    M = np.asarray(M, np.float64)
-    mu = np.asarray(mu, np.float64)
-    nm = np.asarray(norm16, np.float32).astype(np.float64)
-    tgt = np.stack([mu[0] - np.log(M[0]), mu[1], mu[2], mu[3]], axis=1)
-    return (tgt - nm[8:12]) * nm[12:16]
+    """Normalised network targets [n][4] of multipliers mu [4][n]
+    (or_mlp_targets: (mu0 - ln rho, mu1, mu2, mu3), shifted and scaled by
+    norm16[8:12], norm16[12:16])."""
+    M = np.ascontiguousarray(M, np.float64)
+    mu = np.ascontiguousarray(mu, np.float64)
+    n = M.shape[1]
+    nm = _norm(norm16)
+    T = np.zeros((n, 4))
+    lib().or_mlp_targets(_p(M), _p(mu), n, nm.ctypes.data_as(_F32), _p(T))
+    return T
+
+
+def mlp_unnormalise(Y, norm16) -> np.ndarray:
+    """Network outputs Y [n][4] back to (mu0 - ln rho, mu1, mu2, mu3) [4][n]."""
+    Y = np.ascontiguousarray(Y, np.float64)
+    n = Y.shape[0]
+    nm = _norm(norm16)
+    out = np.zeros((4, n))
+    lib().or_mlp_unnormalise(_p(Y), n, nm.ctypes.data_as(_F32), _p(out))
+    return out
 
 
 def mlp_warm_start(params, norm16, M) -> np.ndarray:
-    """Network start (mu0 - ln rho, mu1, mu2, mu3) [4][n] for moments M, with
-    the BF16 rounding points of the GPU kernels emulated."""
-    nm = np.asarray(norm16, np.float32).astype(np.float64)
+    """Network start (mu0 - ln rho, mu1, mu2, mu3) [4][n] for moments M:
+    features, forward pass with the BF16 rounding points of the GPU kernels
+    emulated, outputs unnormalised."""
     y = mlp_forward(params, mlp_features(M, norm16), bf16=True)
-    return (y / nm[12:16] + nm[8:12]).T.copy()
+    return mlp_unnormalise(y, norm16)

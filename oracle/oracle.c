@@ -281,6 +281,53 @@ int or_fstar_newton(const double* M, double tol, int max_iter, double* mu, doubl
 }
 
 /*
+ * Gradient m(f(mu)) - M and Hessian sum_i f_i m_i m_i^T of the dual at mu;
+ * returns the residual max_j |g_j| / rho.
+ */
+static double or_fstar_gh(const double* M, const double* mu, double* g, double H[4][4])
+{
+  int32_t vx[9], vy[9];
+  double w[9], fs[9];
+  or_velocities(9, vx, vy, w);
+  or_fstar_from_mu(mu, fs);
+  for (int a = 0; a < 4; ++a) {
+    g[a] = -M[a];
+    for (int b = 0; b < 4; ++b) H[a][b] = 0.0;
+  }
+  for (int i = 0; i < 9; ++i) {
+    double m[4] = {1.0, vx[i], vy[i], vx[i] * vx[i] + vy[i] * vy[i]};
+    for (int a = 0; a < 4; ++a) {
+      g[a] += fs[i] * m[a];
+      for (int b = 0; b < 4; ++b) H[a][b] += fs[i] * m[a] * m[b];
+    }
+  }
+  double r = 0.0;
+  for (int a = 0; a < 4; ++a)
+    if (fabs(g[a]) / M[0] > r) r = fabs(g[a]) / M[0];
+  return r;
+}
+
+/*
+ * One more undamped Newton update from converged multipliers.  From a
+ * residual of 1e-13 Newton's quadratic convergence leaves O(1e-26) in exact
+ * arithmetic, so the update carries mu to the maximiser of Sec. 2 up to FP64
+ * round-off; it is kept only if the residual does not grow.  Returns the
+ * final residual.
+ */
+double or_fstar_polish(const double* M, double* mu)
+{
+  double g[4], H[4][4], g1[4], H1[4][4];
+  double r0 = or_fstar_gh(M, mu, g, H);
+  double rhs[4] = {-g[0], -g[1], -g[2], -g[3]}, d[4], trial[4];
+  or_solve4(H, rhs, d);
+  for (int a = 0; a < 4; ++a) trial[a] = mu[a] + d[a];
+  double r1 = or_fstar_gh(M, trial, g1, H1);
+  if (!(r1 <= r0)) return r0;
+  for (int a = 0; a < 4; ++a) mu[a] = trial[a];
+  return r1;
+}
+
+/*
  * Independent route to f*_M through its product structure: on D2Q9,
  * |v|^2 = vx^2 + vy^2, so f*_i = A g(vx_i) g(vy_i) with g(0) = 1,
  * g(+-1) = Z X^{+-1} (and Y for the y factor), (A, X, Y, Z) = exp(mu).
@@ -456,6 +503,7 @@ static int or_site_qe(const or_cfg* c, const double* M, double* fs)
     or_qe_entropic_mm(c->Q, rho, u1, u2, fs);
     return 1;
   }
+  or_fstar_polish(M, mu);
   or_fstar_from_mu(mu, fs);
   return 0;
 }
@@ -927,4 +975,70 @@ void or_adam_step(double* p, double* m, double* v, const double* g, int64_t n, i
     double mh = m[i] / c1, vh = v[i] / c2;
     p[i] -= lr * mh / (sqrt(vh) + eps);
   }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inputs and outputs of the warm-start network                             */
+/* ------------------------------------------------------------------------ */
+/*
+ * The network proposes a start for the f*_M solve of Sec. 2 (argmax with
+ * M = (rho, rho u1, rho u2, 2E)).  Its inputs are the moments per unit mass
+ * u1, u2, 2E/rho and |u|^2; its outputs are the multipliers with the
+ * density taken out, (mu0 - ln rho, mu1, mu2, mu3).  By the density
+ * scaling of f*_M (M -> lambda M leaves (mu1, mu2, mu3) and mu0 - ln rho
+ * unchanged, since f* is linear in A = exp(mu0) for fixed X, Y, Z) both
+ * depend on (u1, u2, 2E/rho) only.  They are mapped to O(1) by
+ * x = (v - shift) * scale with the 16 constants norm[0..3] (input shifts),
+ * norm[4..7] (input scales), norm[8..11] (output shifts), norm[12..15]
+ * (output scales).  The normalised inputs are rounded to FP32, the
+ * precision in which the network receives them.  Arrays: M and mu
+ * [4][n] (component-major), X, T and Y [n][4] (sample-major).
+ */
+void or_mlp_features(const double* M, int64_t n, const float* norm, double* X)
+{
+  for (int64_t s = 0; s < n; ++s) {
+    double rho = M[s];
+    double u1 = M[n + s] / rho, u2 = M[2 * n + s] / rho, e = M[3 * n + s] / rho;
+    double v[4] = {u1, u2, e, u1 * u1 + u2 * u2};
+    for (int k = 0; k < 4; ++k) X[4 * s + k] = (double)(float)((v[k] - (double)norm[k]) * (double)norm[4 + k]);
+  }
+}
+
+void or_mlp_targets(const double* M, const double* mu, int64_t n, const float* norm, double* T)
+{
+  for (int64_t s = 0; s < n; ++s) {
+    double v[4] = {mu[s] - log(M[s]), mu[n + s], mu[2 * n + s], mu[3 * n + s]};
+    for (int k = 0; k < 4; ++k) T[4 * s + k] = (v[k] - (double)norm[8 + k]) * (double)norm[12 + k];
+  }
+}
+
+/* network outputs Y back to (mu0 - ln rho, mu1, mu2, mu3), out [4][n] */
+void or_mlp_unnormalise(const double* Y, int64_t n, const float* norm, double* out)
+{
+  for (int64_t s = 0; s < n; ++s)
+    for (int k = 0; k < 4; ++k) out[k * n + s] = Y[4 * s + k] / (double)norm[12 + k] + (double)norm[8 + k];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conservation sums                                                        */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sums over the fluid sites of a state f of the moments rho, rho u1, rho u2
+ * and 2E (Sec. 2: the collision conserves mass and momentum, Sec. 3.1; the
+ * Ehrenfests' step returns a site to the quasiequilibrium with the same
+ * moments), accumulated in long double site by site in index order.
+ */
+void or_sums(const or_cfg* c, const double* f, double* sums)
+{
+  int Q = c->Q;
+  int64_t N = c->nx * c->ny;
+  long double acc[4] = {0.0L, 0.0L, 0.0L, 0.0L};
+  for (int64_t s = 0; s < N; ++s) {
+    if (or_solid(c, s % c->nx, s / c->nx)) continue;
+    double g[9], M[4];
+    for (int i = 0; i < Q; ++i) g[i] = f[(int64_t)i * N + s];
+    or_moments(Q, g, M);
+    for (int a = 0; a < 4; ++a) acc[a] += M[a];
+  }
+  for (int a = 0; a < 4; ++a) sums[a] = (double)acc[a];
 }

@@ -60,6 +60,8 @@ void or_qe_entropic_mm(int Q, double rho, double u1, double u2, double* fs);
 int or_fstar_feasible(const double* M);
 int or_fstar_newton(const double* M, double tol, int max_iter, double* mu, double* resid);
 int or_fstar_scalar(const double* M, double* mu);
+/* one more Newton update from converged multipliers (kept if the residual does not grow) */
+double or_fstar_polish(const double* M, double* mu);
 void or_fstar_from_mu(const double* mu, double* fs);
 
 /* nonequilibrium entropy (generalised Kullback form), long double */
@@ -77,6 +79,8 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS,
 int or_step_sites(const or_cfg* c, const double* f_in, const int64_t* sites, int64_t ns, const int64_t* sel,
                   int64_t nsel, double* out);
 double or_site_dS(const or_cfg* c, const double* f_in, int64_t site);
+/* sums over fluid sites of rho, rho u1, rho u2, 2E of a state f (long double accumulation) */
+void or_sums(const or_cfg* c, const double* f, double* sums);
 
 /* power spectrum of a real signal by the DFT's definition, bins 0..n/2 */
 void or_dft_power(const double* x, int64_t n, double* power);
@@ -90,6 +94,12 @@ double or_mlp_loss_grad(const double* p, const double* x, const double* t, int64
 void or_adam_step(double* p, double* m, double* v, const double* g, int64_t n,
                   int64_t t, double lr, double b1, double b2, double eps);
 double or_bf16_round(double x);
+
+/* inputs (u1, u2, 2E/rho, |u|^2) and outputs (mu0 - ln rho, mu1, mu2, mu3)
+   of the warm-start network, normalised with norm[16] (see oracle.c) */
+void or_mlp_features(const double* M, int64_t n, const float* norm, double* X);
+void or_mlp_targets(const double* M, const double* mu, int64_t n, const float* norm, double* T);
+void or_mlp_unnormalise(const double* Y, int64_t n, const float* norm, double* out);
 
 #ifdef __cplusplus
 }

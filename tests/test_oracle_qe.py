@@ -223,3 +223,42 @@ def test_fstar_infeasible_is_flagged():
     assert oracle.fstar_feasible([1.0, 0.3, 0.2, 0.51])
     mu, it, res = oracle.fstar_newton([1.0, 0.3, 0.2, 0.51], max_iter=200)
     assert it >= 0 and res < 1e-13
+
+
+def test_fstar_polish_reaches_round_off():
+    """One more Newton update from a 1e-13 residual carries f*_M to FP64
+    round-off: the residual drops to a few ulps and f* agrees with the
+    independent long-double scalar route (Sec. 2 argmax) to ~1e-15."""
+    worst_r, worst_f = 0.0, 0.0
+    for M in _random_M(300, 14, umax=0.3, band=0.3):
+        mu, it, res = oracle.fstar_newton(M, 1e-13)
+        assert it >= 0
+        mp, rp = oracle.fstar_polish(M, mu)
+        assert rp <= res
+        fsc = oracle.fstar_from_mu(oracle.fstar_scalar(M))
+        worst_r = max(worst_r, rp)
+        worst_f = max(worst_f, np.abs(oracle.fstar_from_mu(mp) - fsc).max() / M[0])
+    assert worst_r < 2e-15 and worst_f < 2e-15, (worst_r, worst_f)
+
+
+def test_fstar_in_step_is_polished():
+    """Inside the time step f*_M is the polished solve: with delta = 0 and
+    k = N every site is returned to f*_M, and free flight on the periodic
+    lattice carries f*_i(x) to x + v_i; un-rolled, every site matches the
+    scalar route to ~1e-15."""
+    nx, ny = 9, 5
+    cfg = oracle.make_cfg(Q=9, qe=oracle.QE_ENTROPIC_M, nx=nx, ny=ny, nu=1e-3, delta=0.0, k=nx * ny)
+    M = _random_M(nx * ny, 15, umax=0.2, band=0.2)
+    f = np.zeros((9, ny, nx))
+    for s in range(nx * ny):
+        f[:, s // nx, s % nx] = oracle.fstar_from_mu(oracle.fstar_scalar(M[s])) * (1 + 0.01 * np.sin(np.arange(9) + s))
+    o = oracle.step(cfg, f)
+    assert o["n_selected"] == nx * ny
+    vx, vy, _ = oracle.velocities(9)
+    back = np.stack([np.roll(np.roll(o["f"][i], -vy[i], axis=0), -vx[i], axis=1) for i in range(9)])
+    rows = _moment_rows()
+    for s in range(nx * ny):
+        g = f[:, s // nx, s % nx]
+        want = oracle.fstar_from_mu(oracle.fstar_scalar(rows @ g))
+        got = back[:, s // nx, s % nx]
+        assert np.abs(got - want).max() / g.sum() < 2e-15, s

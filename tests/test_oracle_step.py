@@ -380,3 +380,38 @@ def test_outlet_in_per_site_step():
     sites = np.concatenate([np.arange(ny) * nx + nx - 1, np.arange(ny) * nx + nx - 2, np.arange(0, nx * ny, 17)])
     g = oracle.step_sites(cfg, f, sites, out["sel"])
     assert np.array_equal(g, out["f"].reshape(9, -1)[:, sites].T)
+
+
+def test_conservation_sums_pins():
+    """or_sums: a uniform state gives N_fluid x its moments (closed form);
+    solid sites are left out; free flight on a periodic lattice (a
+    permutation) leaves the sums unchanged; a step's reported input sums are
+    the sums of its input; the mass and momentum of a periodic step with
+    Ehrenfests' steps are conserved to round-off (Sec. 3.1, Sec. 3.2)."""
+    rho, u1, u2 = 1.25, 0.0625, -0.03125
+    cfg = oracle.make_cfg(Q=9, nx=12, ny=5, nu=1e-3, solid=(3, 1, 2, 2))
+    fs = oracle.qe_poly(9, rho, u1, u2)
+    f = np.repeat(fs[:, None], 60, axis=1).reshape(9, 5, 12).copy()
+    f[:, 1:3, 3:5] = 7.0                   # solid sites hold anything: not counted
+    s = oracle.sums(cfg, f)
+    nfl = 60 - 4
+    # polynomial QE (cited D2Q9 form): 2E = rho (2/3 + |u|^2)
+    want = [nfl * rho, nfl * rho * u1, nfl * rho * u2, nfl * rho * (2.0 / 3.0 + u1 * u1 + u2 * u2)]
+    assert np.allclose(s, want, rtol=1e-14, atol=1e-14)
+    # D1Q3: no y momentum
+    c3 = oracle.make_cfg(Q=3, nx=7, ny=1)
+    f3 = np.repeat(oracle.qe_poly(3, 0.5, 0.1)[:, None], 7, axis=1).reshape(3, 1, 7)
+    assert np.allclose(oracle.sums(c3, f3), [3.5, 0.35, 0.0, 7 * 0.5 * (1.0 / 3.0 + 0.01)], rtol=1e-14)
+    # free flight is a permutation of each plane
+    cp = oracle.make_cfg(Q=9, nx=13, ny=7, nu=INF)
+    g = _near_eq_state(cp, 21)
+    h = oracle.step(cp, g)["f"]
+    assert np.allclose(oracle.sums(cp, h), oracle.sums(cp, g), rtol=1e-15, atol=1e-15)
+    # the step's input sums, and conservation with resets
+    cq = oracle.make_cfg(Q=9, nx=11, ny=6, nu=1e-3, delta=1e-4, k=5)
+    g = _near_eq_state(cq, 22)
+    o = oracle.step(cq, g)
+    assert np.allclose(o["sums"], oracle.sums(cq, g), rtol=1e-14, atol=1e-14)
+    assert o["n_selected"] > 0
+    a, b = oracle.sums(cq, g), oracle.sums(cq, o["f"])
+    assert np.abs(a[:3] - b[:3]).max() < 1e-13 * a[0]
