@@ -12,8 +12,9 @@ Prints one JSON line:
   value      MLUPS (fluid sites x steps / s) over the timed steps
   roofline   the fused step kernel (k_step): algorithmic bytes per launch
              (72 B per site in FP32, 144 B in FP64: every population read
-             once and written once) / its mean launch duration measured
-             with HIP events on the context's stream during the timed steps
+             once and written once) / its mean launch duration, measured
+             with HIP events on the context's stream around the step kernel
+             of every timed step
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -45,6 +46,21 @@ def traffic_from_profile(workload: str, prec: str, n_sites: int):
     return d.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "cores_available": cores, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(args):
     """The oracle (single thread, FP64 C) on a row band of the same shear
     layer: nx x rows sites, `steps` steps, periodic."""
@@ -60,8 +76,59 @@ def cpu_baseline(args):
     dt = time.perf_counter() - t0
     n = args.cpu_nx * args.cpu_rows
     return {"value": n * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
             "sample": "%d x %d band of the shear layer (same nu, delta, k), %d steps, FP64, %.1f s"
                       % (args.cpu_nx, args.cpu_rows, args.cpu_steps, dt)}
+
+
+def settle(lat, torch, seconds):
+    """Untimed steps for `seconds` (the GPU clocks settle before timing)."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        lat.step(64)
+        torch.cuda.synchronize()
+
+
+def timed_steps(lat, torch, nsteps):
+    """`nsteps` directly launched steps with HIP events around every step
+    kernel.  Returns (wall seconds, summed kernel ms, timed launches)."""
+    lat.set_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.step(nsteps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    ms, n = lat.kernel_time()
+    lat.set_timing(False)
+    return wall, ms, n
+
+
+def fp64_leg(args, torch, lbm, W):
+    """The same shear layer with FP64 populations (144 B per site and step):
+    whole-step rate and the step kernel's HBM roofline from the same timed
+    steps (HIP events around every step kernel)."""
+    d, rho, u = W.shear_layer(nx=args.nx, ny=args.ny)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        lat = lbm.Lattice(lbm.config_from_workload(d, lbm.LBM_FP64, stream=stream.cuda_stream), rho, u)
+    del rho, u
+    n_sites = args.nx * args.ny
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    settle(lat, torch, args.settle_s)
+    dt, k_ms, k_n = timed_steps(lat, torch, args.fp64_steps)
+    ms_step = dt * 1e3 / args.fp64_steps
+    k_avg_ms = k_ms / max(k_n, 1)
+    assert k_n == args.fp64_steps and k_ms <= dt * 1e3, ("inconsistent timing", k_ms, dt * 1e3)
+    st, _, _ = lat.stats()
+    lat.close()
+    ach = 144 * n_sites / (k_avg_ms / 1e3) / 1e9
+    return {"steps": args.fp64_steps, "MLUPS": round(n_sites * args.fp64_steps / dt / 1e6, 1),
+            "ms_per_step": round(ms_step, 4),
+            "roofline": {"bound": "hbm", "kernel": "k_step", "kernel_ms": round(k_avg_ms, 4),
+                         "kernel_launches": k_n, "bytes_per_site": 144, "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)},
+            "nonfinite": st.nonfinite}
 
 
 def cylinder_leg(args, torch, lbm, W, net):
@@ -84,6 +151,8 @@ def cylinder_leg(args, torch, lbm, W, net):
         upd = 0
         sel = 0
         above = 0
+        failed = 0
+        maxres = 0.0
         chunk = 100
         for _ in range(args.cyl_steps // chunk):
             lat.step(chunk)
@@ -91,6 +160,8 @@ def cylinder_leg(args, torch, lbm, W, net):
             fb += st.n_fallback
             upd += st.newton_updates
             above += st.n_above_delta
+            failed += st.n_failed
+            maxres = max(maxres, st.max_resid)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st, _, ds = lat.stats(sel_cap=256)
@@ -100,10 +171,13 @@ def cylinder_leg(args, torch, lbm, W, net):
                      "fallback_sites_sampled_steps": int(fb),
                      "fallback_rate": fb / (fluid * (args.cyl_steps // chunk)),
                      "newton_updates_per_site": upd / (fluid * (args.cyl_steps // chunk)),
+                     "failed_sites_sampled_steps": int(failed), "max_residual_sampled_steps": maxres,
                      "last_step": {"n_above_delta": st.n_above_delta, "n_selected": st.n_selected,
                                    "max_dS": st.max_dS, "kth_dS": st.kth_dS, "nonfinite": st.nonfinite},
                      "selected_total": st.total_selected, "mass": st.mass, "energy": st.energy}
         lat.close()
+        # every sampled step reached the residual target at every site
+        assert failed == 0 and maxres <= 1e-10, (name, failed, maxres)
     return out
 
 
@@ -127,14 +201,17 @@ def channel_leg(args, torch, lbm, W):
         t0 = time.perf_counter()
         done = 0
         nonfinite_in = None
+        last_finite = None
         while done < args.channel_steps:
             n = min(chunk, args.channel_steps - done)
             lat.step(n)
             done += n
             st, _, _ = lat.stats()
             if st.nonfinite:
-                # the run has diverged somewhere in this chunk: stop it there
+                # the run diverged in this chunk; the library kept the state
+                # of the last finite step, whose number stats report
                 nonfinite_in = [done - n, done]
+                last_finite = st.step
                 break
             above += st.n_above_delta
             samples += 1
@@ -144,7 +221,8 @@ def channel_leg(args, torch, lbm, W):
         r = {"steps_run": done, "MLUPS": round(sites * done / dt / 1e6, 1),
              "ms_per_step": round(dt * 1e3 / done, 5),
              "mean_n_above_delta_sampled": round(above / max(samples, 1), 2),
-             "selected_total": st.total_selected, "nonfinite_in_steps": nonfinite_in}
+             "selected_total": st.total_selected, "nonfinite_in_steps": nonfinite_in,
+             "last_finite_step": last_finite}
         if nonfinite_in is None:
             r["mass"] = st.mass
         out["re%d" % re] = r
@@ -266,6 +344,10 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=4096)
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="seconds of untimed steps after the warm-up steps (clock ramp)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 shear-layer leg")
+    ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nx", type=int, default=8192)
     ap.add_argument("--cpu-rows", type=int, default=512)
@@ -329,31 +411,28 @@ def main():
     print("# warmup %d" % args.warmup, file=sys.stderr, flush=True)
     lat.step(args.warmup)
     torch.cuda.synchronize()
-    # kernel timing pass: direct launches with HIP events around the step kernel
-    lat.set_timing(True)
-    print("# %d steps with kernel timing" % args.steps, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.step(args.steps)
-    torch.cuda.synchronize()
-    dt_events = time.perf_counter() - t0
-    k_ms, k_n = lat.kernel_time()
-    lat.set_timing(False)
-    # the headline: the same number of steps as the library runs them by
-    # default (replays of the captured step graphs, no events)
+    settle(lat, torch, args.settle_s)
+    # the timed steps: direct launches with HIP events around every step
+    # kernel on the context's stream, so that the headline rate and the
+    # kernel's roofline come from the same steps
     print("# timed %d steps" % args.steps, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lat.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
+    dt, k_ms, k_n = timed_steps(lat, torch, args.steps)
     st, _, _ = lat.stats()
     ms_per_step = dt * 1e3 / args.steps
     mlups = n_sites * args.steps / dt / 1e6
-
     bytes_per_site = 72 if prec == lbm.LBM_FP32 else 144
-    k_avg_s = k_ms / 1e3 / max(k_n, 1)
-    achieved = bytes_per_site * n_sites / k_avg_s / 1e9
+    k_avg_ms = k_ms / max(k_n, 1)
+    achieved = bytes_per_site * n_sites / (k_avg_ms / 1e3) / 1e9
+    # the step kernel is one part of every timed step
+    assert k_n == args.steps and k_ms <= dt * 1e3, ("inconsistent timing", k_ms, dt * 1e3)
+    # the same number of steps as the library runs them by default (replays
+    # of the captured 32-step graphs, no events)
+    gsteps = max(args.steps, 256)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.step(gsteps)
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t1
     traffic = traffic_from_profile(workload, args.precision, n_sites)
 
     out = {
@@ -374,16 +453,23 @@ def main():
                    "sites": n_sites, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step", "kernel_ms": round(k_avg_s * 1e3, 4),
-                     "bytes_per_site": bytes_per_site},
+                     "traffic": traffic, "kernel": "k_step", "kernel_ms": round(k_avg_ms, 4),
+                     "kernel_launches": k_n, "bytes_per_site": bytes_per_site,
+                     "timing": "HIP events on the context's stream around the k_step of every timed "
+                               "step (%d direct launches)" % k_n},
         "ehrenfest": {"n_above_delta_last": st.n_above_delta, "selected_total": st.total_selected,
                       "mass": st.mass},
-        "kernel_timing_pass_MLUPS": round(n_sites * args.steps / dt_events / 1e6, 1),
+        "settle_s": args.settle_s,
+        "graph_replay": {"steps": gsteps, "MLUPS": round(n_sites * gsteps / dt_graph / 1e6, 1),
+                         "ms_per_step": round(dt_graph * 1e3 / gsteps, 4)},
     }
     if not args.no_active:
         print("# Ehrenfests' steps at full load", file=sys.stderr, flush=True)
         out["ehrenfest_active"] = active_leg(args, torch, lbm, lat, n_sites)
     lat.close()
+    if not args.no_fp64 and prec == lbm.LBM_FP32:
+        print("# fp64 shear layer", file=sys.stderr, flush=True)
+        out["fp64"] = fp64_leg(args, torch, lbm, W)
     if not args.no_channel:
         out["channel_1200x400"] = channel_leg(args, torch, lbm, W)
     if not args.no_fstar:

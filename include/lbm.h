@@ -108,11 +108,16 @@ typedef struct lbm_es_stats {
   int64_t total_selected;/* all steps since init                                   */
   int64_t nonfinite;     /* sticky: a step met non-finite populations              */
   int64_t newton_updates;/* last step, f*_M only: Newton updates over fluid sites  */
+  int64_t n_failed;      /* last step, f*_M only: sites whose damped fallback also
+                            missed the residual target (their last iterate is
+                            used); 0 in a healthy run                             */
   double kth_dS;         /* last step: smallest selected Delta S (0 if none)       */
   double max_dS;         /* last step: largest Delta S above delta (0 if none)     */
   double mass, mom[2], energy; /* FP64 sums over fluid sites of rho, rho u1,
                                   rho u2, 2E of the current pre-collision state
                                   f(x, t) (conservation diagnostics)            */
+  double max_resid;      /* last step, f*_M only: largest final residual
+                            max_j |m_j(f*) - M_j| / rho of a converged site    */
 } lbm_es_stats;
 
 /* Fills *cfg with defaults: D2Q9, polynomial QE, FP32, LBGK, 64 x 64

@@ -56,6 +56,10 @@ struct lbm_ctx {
   bool canonical = true;
   int64_t step = 0;
   bool nonfinite_seen = false;
+  // pinned host copy of the device words C_NONFINITE .. C_BADSTEP, refreshed
+  // asynchronously after every lbm_step call (so that lbm_step can refuse
+  // without waiting for the stream)
+  volatile uint32_t* hflag = nullptr;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -235,6 +239,7 @@ static void ctx_release(lbm_ctx* c) {
                   c->probe_buf, c->probe_n};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->hflag) (void)hipHostFree((void*)c->hflag);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
@@ -243,7 +248,35 @@ static StepArgs args_for(const lbm_ctx* c, int src, int dst) {
   StepArgs a = c->args;
   a.A = c->buf[src];
   a.B = c->buf[dst];
+  a.dst = dst;
   return a;
+}
+
+// After a step met non-finite values the step kernels stop (see
+// raise_nonfinite): the buffer that step read holds the last finite state.
+// Synchronises, and if the device has halted, makes that buffer (and its
+// layout and step number) the context's state; returns whether it had.
+static int take_halt(lbm_ctx* c, bool* halted) {
+  *halted = c->nonfinite_seen;
+  if (c->nonfinite_seen) return LBM_OK;
+  uint32_t w[C_COUNT];
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(w, c->ctr, sizeof(w), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, "halt check: %s", hipGetErrorString(e));
+  if (!w[C_NONFINITE]) return LBM_OK;
+  const uint32_t tag = w[C_NONFINITE] - 1u;
+  c->cur = 1 - (int)(tag & 1u);
+  c->canonical = (tag & 2u) != 0u;
+  c->step = (int64_t)w[C_BADSTEP] - 1;
+  if (c->probe_n) {
+    unsigned long long pn = 0;
+    e = hipMemcpy(&pn, c->probe_n, sizeof(pn), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, "halt check: %s", hipGetErrorString(e));
+    c->probe_total = (int64_t)pn;
+  }
+  c->nonfinite_seen = true;
+  *halted = true;
+  return LBM_OK;
 }
 
 // one time step from buffer src into buffer dst.  For the f*_M
@@ -345,6 +378,15 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   ALLOC(c->sel_ds, sizeof(double) * kcap);
   ALLOC(c->st, sizeof(DevStats));
   ALLOC(c->partials, sizeof(double) * 4 * 1024);
+  {
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+      ctx_release(c);
+      return fail(LBM_E_NOMEM, "pinned host word");
+    }
+    c->hflag = (volatile uint32_t*)hp;
+    for (int i = 0; i < 4; ++i) c->hflag[i] = 0u;
+  }
   if (cfg->qe == LBM_QE_ENTROPIC_M) {
     ALLOC(c->Mbuf, sizeof(double) * 4 * ncap);
     ALLOC(c->mubuf, sizeof(double) * 4 * ncap);
@@ -367,6 +409,8 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
     f.tol32 = 2e-6f;
     f.max32 = 16;
     f.max64 = 6;
+    // FP64 contexts carry every solve to round-off (one more Newton update)
+    f.polish = cfg->precision == LBM_FP64 ? 1 : 0;
     c->fkind = cfg->fstar_start == LBM_START_CLOSED_FORM ? START_CLOSED
                : cfg->fstar_start == LBM_START_MLP        ? START_WARM
                : cfg->fstar_start == LBM_START_PREV       ? START_PREV
@@ -410,6 +454,8 @@ void lbm_struct_sizes(int64_t* config_size, int64_t* stats_size) {
   if (config_size) *config_size = (int64_t)sizeof(lbm_config);
   if (stats_size) *stats_size = (int64_t)sizeof(lbm_es_stats);
 }
+
+static int step_run(lbm_ctx* c, int64_t n);
 
 static int ensure_graph(lbm_ctx* c, int from) {
   if (c->gexec[from]) return LBM_OK;
@@ -463,7 +509,22 @@ static int drain_events(lbm_ctx* c) {
 int lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
   if (n < 0) return fail(LBM_E_INVAL, "nsteps must be >= 0");
-  if (c->nonfinite_seen) return fail(LBM_E_NONFINITE, "non-finite populations were reported; set new populations");
+  int rc;
+  if (!c->nonfinite_seen && c->hflag[0] != 0u) {
+    bool h = false;
+    if ((rc = take_halt(c, &h))) return rc;
+  }
+  if (c->nonfinite_seen)
+    return fail(LBM_E_NONFINITE, "step %lld met non-finite populations (the state of step %lld is kept); "
+                "set new populations", (long long)(c->step + 1), (long long)c->step);
+  rc = step_run(c, n);
+  // refresh the host copy of the halt words behind the queued steps
+  HIPCHK(hipMemcpyAsync((void*)c->hflag, c->ctr + C_NONFINITE, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                        c->stream));
+  return rc;
+}
+
+static int step_run(lbm_ctx* c, int64_t n) {
   int rc;
   while (n > 0) {
     if (c->canonical || c->timing) {
@@ -500,6 +561,9 @@ int lbm_step(lbm_ctx* c, int64_t n) {
 
 int lbm_get_populations(lbm_ctx* c, void* f) {
   if (!c || !f) return fail(LBM_E_INVAL, "ctx and f are required");
+  bool h;
+  int rc = take_halt(c, &h);
+  if (rc) return rc;
   HIPCHK(launch_get(args_for(c, c->cur, c->cur), !c->canonical, f, c->stream));
   return LBM_OK;
 }
@@ -514,6 +578,7 @@ int lbm_set_populations(lbm_ctx* c, const void* f) {
   c->canonical = true;
   c->step = 0;
   c->nonfinite_seen = false;
+  for (int i = 0; i < 4; ++i) c->hflag[i] = 0u;
   if (flags[C_SETBAD]) {
     c->nonfinite_seen = true;
     return fail(LBM_E_NONFINITE, "populations hold non-finite values");
@@ -523,6 +588,9 @@ int lbm_set_populations(lbm_ctx* c, const void* f) {
 
 int lbm_moments(lbm_ctx* c, double* rho, double* rhou, double* e2) {
   if (!c) return fail(LBM_E_INVAL, "ctx is NULL");
+  bool h;
+  int rc = take_halt(c, &h);
+  if (rc) return rc;
   HIPCHK(launch_moments(args_for(c, c->cur, c->cur), !c->canonical, rho, rhou, e2, c->stream));
   return LBM_OK;
 }
@@ -530,6 +598,9 @@ int lbm_moments(lbm_ctx* c, double* rho, double* rhou, double* e2) {
 int lbm_ehrenfest_stats(lbm_ctx* c, lbm_es_stats* out, int64_t* sel, double* sel_dS, int64_t cap) {
   if (!c || !out) return fail(LBM_E_INVAL, "ctx and out are required");
   if (cap < 0) return fail(LBM_E_INVAL, "sel_cap must be >= 0");
+  bool halted;
+  int rc = take_halt(c, &halted);
+  if (rc) return rc;
   HIPCHK(launch_sums(args_for(c, c->cur, c->cur), !c->canonical, c->stream));
   DevStats st;
   uint32_t ctr[C_COUNT];
@@ -549,16 +620,17 @@ int lbm_ehrenfest_stats(lbm_ctx* c, lbm_es_stats* out, int64_t* sel, double* sel
     const FstarStats fs = fstar_stats_total(slots);
     out->n_fallback = (int64_t)(fs.fallback + fs.infeasible);
     out->newton_updates = (int64_t)(fs.sum32 + fs.sum64);
+    out->n_failed = (int64_t)fs.failed;
+    std::memcpy(&out->max_resid, &fs.maxres_bits, sizeof(double));
   }
   out->total_selected = (int64_t)st.total_sel;
-  out->nonfinite = ctr[C_NONFINITE] ? 1 : 0;
+  out->nonfinite = halted ? 1 : 0;
   out->kth_dS = st.kth;
   out->max_dS = st.max;
   out->mass = st.sums[0];
   out->mom[0] = st.sums[1];
   out->mom[1] = st.sums[2];
   out->energy = st.sums[3];
-  if (out->nonfinite) c->nonfinite_seen = true;
   if ((sel || sel_dS) && st.n_sel > 0 && cap > 0) {
     std::vector<uint32_t> s(st.n_sel);
     std::vector<double> d(st.n_sel);

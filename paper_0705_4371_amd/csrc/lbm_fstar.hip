@@ -66,6 +66,7 @@ __global__ __launch_bounds__(64) void k_fstar_fallback(FstarArgs a) {
     FS<double> s;
     double res = 0.0;
     const int it = newton64_damped(u1, u2, e, a.tol, 200, s, res);
+    if (it >= 0 && a.polish) res = polish_once(s, u1, u2, e);
     write_mu(a, i, rho, s);
     if (a.status) a.status[i] = it >= 0 ? 1 : 3;
     FstarStats& S = stat_slot(a.stats);

@@ -57,6 +57,8 @@ struct FstarArgs {
   double tol;           // FP64 residual target
   float tol32;          // FP32 phase target
   int max32, max64;     // iteration budgets of the two phases
+  int polish;           // 1: one more FP64 Newton update after convergence
+                        // (to round-off; FP64 time-step contexts)
 };
 
 hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s);

@@ -143,6 +143,22 @@ __device__ __forceinline__ FS<double> polish64(FS<double> s, double u1, double u
   return s;
 }
 
+// One more undamped FP64 Newton update from a converged state: from a
+// residual <= 1e-10 the update leaves ~1e-20 in exact arithmetic, so the
+// maximiser of Sec. 2 is reached to FP64 round-off.  Returns the residual
+// at the updated state.
+__device__ __forceinline__ double polish_once(FS<double>& s, double u1, double u2, double e) {
+  double g[4], H[10], d[4];
+  fsys<double>(s, u1, u2, e, g, H);
+  fsolve<double>(H, g, d);
+  s.a *= exp_step(d[0]);
+  s.X *= exp_step(d[1]);
+  s.Y *= exp_step(d[2]);
+  s.Z *= exp_step(d[3]);
+  fsys_grad<double>(s, u1, u2, e, g);
+  return resid(g);
+}
+
 // f*_i = rho a g(vx) g(vy) on D2Q9 (paper numbering) from the product-form state
 template <typename T>
 __device__ __forceinline__ void fstar_pop(T rho_a, T X, T Y, T Z, T* fs) {

@@ -185,6 +185,10 @@ __device__ __forceinline__ void solve_site(const FstarArgs& a, int64_t i, double
       }
     }
     if (ok) {
+      if (a.polish) {
+        res = polish_once(t, u1, u2, e);
+        ++it64;
+      }
       write_mu(a, i, rho, t);
       if (st) { st[0] = t.a * rho; st[1] = t.X; st[2] = t.Y; st[3] = t.Z; }
       if (a.status) a.status[i] = 0;

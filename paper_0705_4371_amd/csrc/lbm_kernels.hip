@@ -166,6 +166,7 @@ __global__ __launch_bounds__(256) void k_clear(StepArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T, bool PULL>
 __global__ __launch_bounds__(STEP_TX) void k_moments_M(StepArgs a) {
+  if (halted(a)) return;
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
   const int64_t N = g.nx * g.ny;

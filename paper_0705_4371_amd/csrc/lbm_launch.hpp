@@ -30,12 +30,16 @@ enum : int {
   C_SCREEN = 0,    // sites that passed the FP32 screen this step
   C_CAND = 1,      // sites with FP64 Delta S > delta this step
   C_INVALID = 2,   // candidates with Delta S = +inf
-  C_NONFINITE = 3, // sticky: a non-finite moment sum was seen
+  C_NONFINITE = 3, // sticky halt: 0, or 1 + (buffer written by the first step
+                   // that met non-finite values) + 2 (if that step read the
+                   // canonical layout); every later step kernel returns at once
   C_NSEL0 = 4,     // sites selected by k_partition (above the bin b*)
   C_SETBAD = 5,    // set_populations met a non-finite value
+  C_BADSTEP = 6,   // number of that first non-finite step (1 = the first step)
   C_BSTAR = 7,     // histogram bin holding the k-th largest key
   C_R = 8,         // keys still to take from bin b*
   C_NBND = 9,      // candidates in bin b* (boundary list)
+  C_STEP0 = 10,    // C_STEP0 + d: number of the last step that wrote buffer d
   C_COUNT = 16
 };
 
@@ -46,6 +50,7 @@ constexpr int STEP_TX = 256;  // sites per step-kernel block (one row segment)
 struct StepArgs {
   const void* A;   // state read this step
   void* B;         // state written this step
+  int dst;         // index (0 or 1) of the buffer B
   Geom g;
   uint32_t* ctr;
   uint32_t* screen;

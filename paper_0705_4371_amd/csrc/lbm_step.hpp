@@ -196,9 +196,11 @@ __device__ __forceinline__ bool screen_entropic(const StepArgs& a, const T* f, c
 
 // LBGK collision f' = f + 2 beta (f* - f) (eq. (lbgkLB)), or ELBM
 // f' = f + alpha beta (f* - f) (eq. (elbmLB)), written at the origin site
-// with non-temporal stores (nothing reads it again in this step)
+// with non-temporal stores (nothing reads it again in this step); returns
+// the sum of the written values (non-finite iff one of them is, or they
+// overflow)
 template <typename T, int Q, bool ELBM>
-__device__ __forceinline__ void collide_store(const StepArgs& a, int64_t x, int64_t y, const T* f, const T* fs) {
+__device__ __forceinline__ T collide_store(const StepArgs& a, int64_t x, int64_t y, const T* f, const T* fs) {
   T* __restrict__ B = (T*)a.B;
   T b2 = T(a.g.beta2);
   if constexpr (ELBM) {
@@ -207,12 +209,37 @@ __device__ __forceinline__ void collide_store(const StepArgs& a, int64_t x, int6
     for (int i = 0; i < Q; ++i) { fd[i] = (double)f[i]; fsd[i] = (double)fs[i]; }
     b2 = T(0.5 * a.g.beta2 * elbm_alpha<Q>(fd, fsd));
   }
+  T sum = T(0);
   #pragma unroll
-  for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(T(f[i] + b2 * (fs[i] - f[i])), &B[sidx<Q>(a.g, x, y, i)]);
+  for (int i = 0; i < Q; ++i) {
+    const T v = f[i] + b2 * (fs[i] - f[i]);
+    sum += v;
+    __builtin_nontemporal_store(v, &B[sidx<Q>(a.g, x, y, i)]);
+  }
+  return sum;
+}
+
+// Non-finite halt.  The first step that meets non-finite values (in the
+// populations it reads or writes) records itself in C_NONFINITE / C_BADSTEP;
+// every step kernel launched after that returns at once, so the buffer the
+// step read -- the last finite state -- is kept for the host to recover.
+__device__ __forceinline__ bool halted(const StepArgs& a) { return a.ctr[C_NONFINITE] != 0u; }
+
+template <bool PULL>
+__device__ __forceinline__ void raise_nonfinite(const StepArgs& a) {
+  const uint32_t tag = 1u + (uint32_t)a.dst + (PULL ? 0u : 2u);
+  if (atomicCAS(&a.ctr[C_NONFINITE], 0u, tag) == 0u) a.ctr[C_BADSTEP] = a.ctr[C_STEP0 + 1 - a.dst] + 1u;
+}
+
+// step number of buffer dst: one more than that of the buffer read (the
+// latter is not written during this step, so every block sees one value)
+__device__ __forceinline__ void count_step(const StepArgs& a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr[C_STEP0 + a.dst] = a.ctr[C_STEP0 + 1 - a.dst] + 1u;
 }
 
 // the screened sites of the workgroup are appended with one atomic, and the
-// sticky non-finite flag is raised (every thread of the block calls this)
+// non-finite halt is raised (every thread of the block calls this)
+template <bool PULL>
 __device__ __forceinline__ void append_screened(const StepArgs& a, bool scr, uint32_t site, bool bad) {
   if (__syncthreads_or(scr)) {
     __shared__ uint32_t s_cnt[4], s_base;
@@ -221,11 +248,16 @@ __device__ __forceinline__ void append_screened(const StepArgs& a, bool scr, uin
   }
   // once the flag is set, waves only read it (no atomic storm on one word)
   if (__ballot(bad) && (threadIdx.x & 63) == 0 && __atomic_load_n(&a.ctr[C_NONFINITE], __ATOMIC_RELAXED) == 0u)
-    atomicOr(&a.ctr[C_NONFINITE], 1u);
+    raise_nonfinite<PULL>(a);
 }
 
 template <typename T, int Q, int QE, bool PULL, bool ELBM = false>
 __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
+  // another workgroup of this very step may raise the halt while this one
+  // runs, so each wave decides for itself and skips its writes (not the
+  // workgroup's barriers)
+  const bool live = !halted(a);
+  count_step(a);
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
   const int64_t b = xcd_remap(blockIdx.x, a.nblocks);
@@ -238,7 +270,7 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
   load_segment_site<T, Q, PULL>(A, g, x0, x, y, fluid, f);
 
   const Moments<Q, T> m = moments<Q, T>(f);
-  if (fluid && x + y * g.nx == a.probe) probe_sample<Q, T>(a, m);
+  if (live && fluid && x + y * g.nx == a.probe) probe_sample<Q, T>(a, m);
   T fs[Q], pb[Q];
   const T inv = inv_of(m.rho);
   const T ux = m.jx * inv, uy = m.jy * inv;
@@ -268,8 +300,10 @@ __global__ __launch_bounds__(STEP_TX) void k_step(StepArgs a) {
     }
   }
 
-  if (fluid) collide_store<T, Q, ELBM>(a, x, y, f, fs);
-  append_screened(a, scr, (uint32_t)(x + y * g.nx), fluid && !__builtin_isfinite(m.rho));
+  T osum = T(0);
+  if (live && fluid) osum = collide_store<T, Q, ELBM>(a, x, y, f, fs);
+  append_screened<PULL>(a, live && scr, (uint32_t)(x + y * g.nx),
+                        live && fluid && !(__builtin_isfinite(m.rho) && __builtin_isfinite(osum)));
 }
 
 // ---------------------------------------------------------------------------
@@ -371,6 +405,7 @@ constexpr int RANK_W = RANK_TX / 64;
 
 template <typename T, int Q, int QE, bool PULL>
 __device__ __forceinline__ void rank_body(const StepArgs& a) {
+  if (halted(a)) return;  // (not raised by the selection kernels: uniform)
   __shared__ uint32_t s_hist[HIST_BINS / 2];  // two 16-bit counts per word
   __shared__ Cand s_cand[RANK_BUF];
   __shared__ uint32_t s_cnt[RANK_W], s_inv[RANK_W], s_nc, s_gbase;
@@ -511,6 +546,7 @@ __device__ __forceinline__ void find_bstar(const uint32_t* __restrict__ hist, ui
 
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
+  if (halted(a)) return;
   __shared__ uint32_t s_cnt[4], s_base, s_bstar, s_r;
   __shared__ uint32_t s_scan[256];
   __shared__ unsigned long long s_mx[4], s_mn[4];
@@ -577,6 +613,7 @@ constexpr uint32_t REFINE_LDS = 8192;
 
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
+  if (halted(a)) return;
   __shared__ uint32_t s_hist[256], s_scan[256];
   __shared__ uint32_t s_nsel, s_dig, s_rr, s_exact;
   __shared__ unsigned long long s_mn[4];
@@ -745,6 +782,7 @@ __device__ __forceinline__ uint32_t append_one(bool flag, uint32_t* s_total, uin
 
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(ONE_TX) void k_select_one(StepArgs a) {
+  if (halted(a)) return;
   __shared__ uint32_t s_hist[HIST_BINS];
   __shared__ uint32_t s_cnt[ONE_TX / 64];
   __shared__ uint32_t s_nc, s_ninv, s_nsel, s_nbnd, s_bstar, s_r, s_dig, s_rr, s_exact;
@@ -908,6 +946,10 @@ __global__ __launch_bounds__(ONE_TX) void k_select_one(StepArgs a) {
 
 template <typename T, bool PULL, int START, bool ELBM>
 __global__ __launch_bounds__(STEP_TX) void k_fstep(StepArgs s, FstarArgs a) {
+  // a workgroup-uniform decision (the halt may be raised meanwhile by
+  // another workgroup of this step)
+  if (__syncthreads_or(halted(s))) return;
+  count_step(s);
   __shared__ SolveAcc sh;
   if (threadIdx.x < sizeof(SolveAcc) / 4) ((uint32_t*)&sh)[threadIdx.x] = 0;
   __syncthreads();
@@ -929,6 +971,7 @@ __global__ __launch_bounds__(STEP_TX) void k_fstep(StepArgs s, FstarArgs a) {
     if (fluid && i == s.probe) probe_sample<9, T>(s, m);
     int it32 = 0, it64 = 0;
     bool scr = false;
+    T osum = T(0);
     if (fluid) {
       double fd[9];
       #pragma unroll
@@ -949,13 +992,14 @@ __global__ __launch_bounds__(STEP_TX) void k_fstep(StepArgs s, FstarArgs a) {
         T fs[9];
         fstar_pop<T>((T)st[0], (T)st[1], (T)st[2], (T)st[3], fs);
         if (g.ds_on) scr = screen_entropic<9, T>(s, f, fs, m.rho);
-        collide_store<T, 9, ELBM>(s, x, y, f, fs);
+        osum = collide_store<T, 9, ELBM>(s, x, y, f, fs);
       }
       sum32 += (uint32_t)it32;
       sum64 += (uint32_t)it64;
     }
     solve_hist(sh, fluid, it32 + it64);
-    append_screened(s, scr, (uint32_t)i, fluid && !__builtin_isfinite(m.rho));
+    append_screened<PULL>(s, scr, (uint32_t)i,
+                          fluid && !(__builtin_isfinite(m.rho) && __builtin_isfinite(osum)));
   }
   solve_flush(a, sh, sum32, sum64, ninf, maxres);
 }
@@ -964,6 +1008,7 @@ __global__ __launch_bounds__(STEP_TX) void k_fstep(StepArgs s, FstarArgs a) {
 // their moments, then the same screen and collision (f(x, t) pulled again)
 template <typename T, bool PULL, bool ELBM>
 __global__ __launch_bounds__(64) void k_fstep_fallback(StepArgs s, FstarArgs a) {
+  if (halted(s)) return;  // single-wave workgroups: no barrier to keep
   const uint32_t nf = a.ctr[0];
   const int64_t n = a.n;
   const Geom& g = s.g;
@@ -973,6 +1018,7 @@ __global__ __launch_bounds__(64) void k_fstep_fallback(StepArgs s, FstarArgs a) 
     FS<double> q;
     double res = 0.0;
     const int it = newton64_damped(u1, u2, e, a.tol, 200, q, res);
+    if (it >= 0 && a.polish) res = polish_once(q, u1, u2, e);
     write_mu(a, i, rho, q);
     if (a.status) a.status[i] = it >= 0 ? 1 : 3;
     FstarStats& S = stat_slot(a.stats);
@@ -986,7 +1032,8 @@ __global__ __launch_bounds__(64) void k_fstep_fallback(StepArgs s, FstarArgs a) 
     fstar_pop<T>((T)(q.a * rho), (T)q.X, (T)q.Y, (T)q.Z, fs);
     const Moments<9, T> m = moments<9, T>(f);
     if (g.ds_on && screen_entropic<9, T>(s, f, fs, m.rho)) s.screen[atomicAdd(&s.ctr[C_SCREEN], 1u)] = (uint32_t)i;
-    collide_store<T, 9, ELBM>(s, x, y, f, fs);
+    const T osum = collide_store<T, 9, ELBM>(s, x, y, f, fs);
+    if (!(__builtin_isfinite(m.rho) && __builtin_isfinite(osum))) raise_nonfinite<PULL>(s);
   }
 }
 

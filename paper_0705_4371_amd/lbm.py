@@ -44,9 +44,9 @@ class lbm_es_stats(C.Structure):
     _fields_ = [
         ("step", C.c_int64), ("n_above_delta", C.c_int64), ("n_selected", C.c_int64),
         ("n_invalid", C.c_int64), ("n_fallback", C.c_int64), ("total_selected", C.c_int64),
-        ("nonfinite", C.c_int64), ("newton_updates", C.c_int64),
+        ("nonfinite", C.c_int64), ("newton_updates", C.c_int64), ("n_failed", C.c_int64),
         ("kth_dS", C.c_double), ("max_dS", C.c_double), ("mass", C.c_double),
-        ("mom", C.c_double * 2), ("energy", C.c_double),
+        ("mom", C.c_double * 2), ("energy", C.c_double), ("max_resid", C.c_double),
     ]
 
 

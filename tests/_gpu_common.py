@@ -94,11 +94,23 @@ def compare_step(lat, d, f_in, tol, label=""):
     scale = np.abs(o["f"]).max()
     err = np.abs(g - o["f"])[mask].max() / scale
     assert err <= tol, "%s population rel err %g > %g" % (label, err, tol)
-    # FP64 conservation sums of the current state (computed on the GPU) vs
-    # the same sums of the GPU populations in numpy (summation order only)
+    # FP64 conservation sums of f(t+1) computed on the GPU (Sec. 3.1: the
+    # collision conserves mass and momentum; Sec. 3.2: a reset keeps the
+    # moments) against the FP64 oracle's sums of its own f(t+1): 1e-12 of
+    # the mass in FP64 contexts, 1e-6 in FP32 (the FP32 step's rounding of
+    # the populations; the summation itself is FP64 on both sides)
+    fp64 = lat.cfg.precision == 1
     sums = np.array([st.mass, st.mom[0], st.mom[1], st.energy])
-    vx, vy, _ = oracle.velocities(d["Q"])
-    want = np.array([g.sum(), np.tensordot(vx, g, 1).sum(), np.tensordot(vy, g, 1).sum(),
-                     np.tensordot(vx * vx + vy * vy, g, 1).sum()])
-    assert np.all(np.abs(sums - want) <= 1e-12 * g.sum()), (label, sums, want)
+    want = oracle.sums(oc, o["f"])
+    own = oracle.sums(oc, g)
+    err = np.abs(sums - want) / want[0]
+    SUMS_ERR.append((label, "fp64" if fp64 else "fp32", err.max()))
+    assert err.max() <= (1e-12 if fp64 else 1e-6), (label, sums, want, err)
+    # the GPU's summation order against the oracle's on the same populations
+    assert np.abs(sums - own).max() <= 1e-13 * own[0], (label, sums, own)
     return g, o, st
+
+
+# (label, precision, max relative error of the four conservation sums
+# against the oracle) of every compare_step of the session
+SUMS_ERR = []
