@@ -289,6 +289,30 @@ int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_
                     const lbm_mlp* net, uint8_t* iters, uint8_t* status, lbm_solve_stats* stats);
 void lbm_fstar_free(lbm_fstar* s);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lbm_fstar_solve without a solver handle.  Arguments as lbm_fstar_solve,
+ * with the tolerances of lbm_fstar_set_tolerance given directly, queued on
+ * `stream` (hipStream_t, 0: null stream); the same kernels, so the same
+ * results bit for bit.  It allocates nothing: its scratch (failure counter,
+ * statistics, failure list for up to LBM_FSTAR_STATIC_MAX_N sites, network
+ * start for up to LBM_FSTAR_STATIC_MLP_MAX sites: 48 MB) is static device
+ * memory of the library, one copy per GPU, held until the process ends,
+ * and cleared by a kernel at the start of every call (no memset).  All calls
+ * on one GPU share that scratch: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must not be issued.  Limits
+ * (LBM_E_INVAL beyond them): n <= LBM_FSTAR_STATIC_MAX_N, and
+ * n <= LBM_FSTAR_STATIC_MLP_MAX for LBM_START_MLP.  stats (host, optional)
+ * synchronises the stream (and returns LBM_E_NOCONV if a site failed); with
+ * stats == NULL the call only queues kernels.
+ */
+#define LBM_FSTAR_STATIC_MLP_MAX (1 << 20)
+#define LBM_FSTAR_STATIC_MAX_N (1 << 23)
+int lbm_fstar_solve_static(const double* M, int64_t n, double* mu, int32_t start, const lbm_mlp* net,
+                           double tol, double tol32, int32_t max32, int32_t max64, uint8_t* iters,
+                           uint8_t* status, lbm_solve_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned Newton warm start: MLP 4 -> 64 -> 64 -> 4, SiLU, BF16 matrix-core
  * products with FP32 accumulation, FP32 master weights and Adam moments.

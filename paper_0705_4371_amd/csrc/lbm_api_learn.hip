@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -34,6 +35,63 @@ static uint64_t splitmix64(uint64_t x) {
 }
 static double u01(uint64_t seed, uint64_t i) {
   return (double)(splitmix64(seed * 0x9E3779B97F4A7C15ull ^ i) >> 11) * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of lbm_fstar_solve_static, in the library's own device memory
+// (each GPU holds one copy until the process ends): the failure counter at
+// byte 0, the FSTAR_STAT_SLOTS copies of the statistics at byte 256, the
+// failure list (uint32 [n]) for up to LBM_FSTAR_STATIC_MAX_N sites from
+// byte STATIC_FAIL_OFF, and the network's start (float [4][n]) for up to
+// LBM_FSTAR_STATIC_MLP_MAX sites from byte STATIC_WARM_OFF: 48 MB in all.
+// In host code `scratch` names a host-side stand-in; its device address is
+// taken once per device with hipGetSymbolAddress and only that address is
+// used.
+// ---------------------------------------------------------------------------
+constexpr size_t STATIC_STATS_OFF = 256;
+constexpr size_t STATIC_FAIL_OFF = 4096;
+constexpr size_t STATIC_WARM_OFF = STATIC_FAIL_OFF + sizeof(uint32_t) * (size_t)LBM_FSTAR_STATIC_MAX_N;
+constexpr size_t STATIC_BYTES = STATIC_WARM_OFF + sizeof(float) * 4 * (size_t)LBM_FSTAR_STATIC_MLP_MAX;
+static_assert(STATIC_STATS_OFF + sizeof(FstarStats) * FSTAR_STAT_SLOTS <= STATIC_FAIL_OFF, "scratch layout");
+static_assert(STATIC_WARM_OFF % 256 == 0, "scratch layout");
+
+static __device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[STATIC_MAX_DEVICES];
+
+// the current device's address of `scratch` (looked up once per device)
+static int static_scratch(unsigned char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return lbm_internal_fail(LBM_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return lbm_internal_fail(LBM_E_DEVICE, "device %d not supported", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return lbm_internal_fail(LBM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+static void fill_solve_stats(const FstarStats& h, int64_t n, lbm_solve_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  st->n = n;
+  st->n_infeasible = (int64_t)h.infeasible;
+  st->n_fallback = (int64_t)h.fallback;
+  st->n_failed = (int64_t)h.failed;
+  for (int i = 0; i < 16; ++i) st->iter_hist[i] = (int64_t)h.hist[i];
+  const double nf = (double)(n - (int64_t)h.infeasible);
+  st->mean_fp32_iters = nf > 0 ? (double)h.sum32 / nf : 0.0;
+  st->mean_fp64_iters = nf > 0 ? (double)h.sum64 / nf : 0.0;
+  double mr;
+  std::memcpy(&mr, &h.maxres_bits, 8);
+  st->max_resid = mr;
 }
 
 extern "C" {
@@ -119,18 +177,63 @@ int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_
     HIPCHK(hipMemcpyAsync(slots, s->stats, sizeof(slots), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     const FstarStats h = fstar_stats_total(slots);
-    std::memset(st, 0, sizeof(*st));
-    st->n = n;
-    st->n_infeasible = (int64_t)h.infeasible;
-    st->n_fallback = (int64_t)h.fallback;
-    st->n_failed = (int64_t)h.failed;
-    for (int i = 0; i < 16; ++i) st->iter_hist[i] = (int64_t)h.hist[i];
-    const double nf = (double)(n - (int64_t)h.infeasible);
-    st->mean_fp32_iters = nf > 0 ? (double)h.sum32 / nf : 0.0;
-    st->mean_fp64_iters = nf > 0 ? (double)h.sum64 / nf : 0.0;
-    double mr;
-    std::memcpy(&mr, &h.maxres_bits, 8);
-    st->max_resid = mr;
+    fill_solve_stats(h, n, st);
+    if (h.failed) return lbm_internal_fail(LBM_E_NOCONV, "%llu sites above the tolerance", (unsigned long long)h.failed);
+  }
+  return LBM_OK;
+}
+
+int lbm_fstar_solve_static(const double* M, int64_t n, double* mu, int32_t start, const lbm_mlp* net, double tol,
+                           double tol32, int32_t max32, int32_t max64, uint8_t* iters, uint8_t* status,
+                           lbm_solve_stats* st, void* stream) {
+  if (!M || !mu) return lbm_internal_fail(LBM_E_INVAL, "M and mu are required");
+  if (n < 0 || n > LBM_FSTAR_STATIC_MAX_N)
+    return lbm_internal_fail(LBM_E_INVAL, "n must be in [0, %lld] (got %lld)", (long long)LBM_FSTAR_STATIC_MAX_N,
+                             (long long)n);
+  if (start != LBM_START_DEFAULT && start != LBM_START_CLOSED_FORM && start != LBM_START_MLP &&
+      start != LBM_START_PREV)
+    return lbm_internal_fail(LBM_E_INVAL, "start must be one of LBM_START_*");
+  if (start == LBM_START_MLP && !net) return lbm_internal_fail(LBM_E_INVAL, "LBM_START_MLP needs a network");
+  if (start == LBM_START_MLP && n > LBM_FSTAR_STATIC_MLP_MAX)
+    return lbm_internal_fail(LBM_E_INVAL,
+                             "LBM_START_MLP: the static scratch holds the network start of at most %d sites "
+                             "(got %lld); use lbm_fstar_solve",
+                             LBM_FSTAR_STATIC_MLP_MAX, (long long)n);
+  if (!(tol > 0.0) || !(tol32 > 0.0) || max32 < 0 || max64 < 1 || max32 > 64 || max64 > 64)
+    return lbm_internal_fail(LBM_E_INVAL, "need tol > 0, tol32 > 0, 0 <= max32 <= 64, 1 <= max64 <= 64");
+  unsigned char* base = nullptr;
+  int rc = static_scratch(&base);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  FstarArgs a{};
+  a.M = M;
+  a.n = n;
+  a.mu = mu;
+  float* warm = (float*)(base + STATIC_WARM_OFF);
+  a.warm = warm;
+  a.iters = iters;
+  a.status = status;
+  a.ctr = (uint32_t*)base;
+  a.fail_list = (uint32_t*)(base + STATIC_FAIL_OFF);
+  a.stats = (FstarStats*)(base + STATIC_STATS_OFF);
+  a.tol = tol;
+  a.tol32 = (float)tol32;
+  a.max32 = max32;
+  a.max64 = max64;
+  int kind = START_REST;
+  if (start == LBM_START_CLOSED_FORM) kind = START_CLOSED;
+  if (start == LBM_START_PREV) kind = START_PREV;
+  if (start == LBM_START_MLP) {
+    kind = START_WARM;
+    if (n > 0) HIPCHK(launch_mlp_warm(net->params, net->norm, M, n, warm, s));
+  }
+  HIPCHK(launch_fstar(a, kind, s));
+  if (st) {
+    FstarStats slots[FSTAR_STAT_SLOTS];
+    HIPCHK(hipMemcpyAsync(slots, a.stats, sizeof(slots), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const FstarStats h = fstar_stats_total(slots);
+    fill_solve_stats(h, n, st);
     if (h.failed) return lbm_internal_fail(LBM_E_NOCONV, "%llu sites above the tolerance", (unsigned long long)h.failed);
   }
   return LBM_OK;

@@ -63,16 +63,7 @@ __global__ __launch_bounds__(64) void k_fstar_fallback(FstarArgs a) {
   for (uint32_t t = blockIdx.x * 64u + threadIdx.x; t < nf; t += gridDim.x * 64u) {
     const int64_t i = a.fail_list[t];
     const double rho = a.M[i], u1 = a.M[n + i] / rho, u2 = a.M[2 * n + i] / rho, e = a.M[3 * n + i] / rho;
-    FS<double> s;
-    double res = 0.0;
-    const int it = newton64_damped(u1, u2, e, a.tol, 200, s, res);
-    if (it >= 0 && a.polish) res = polish_once(s, u1, u2, e);
-    write_mu(a, i, rho, s);
-    if (a.status) a.status[i] = it >= 0 ? 1 : 3;
-    FstarStats& S = stat_slot(a.stats);
-    atomicAdd(&S.fallback, 1ull);
-    if (it < 0) atomicAdd(&S.failed, 1ull);
-    else atomicMax(&S.maxres_bits, (unsigned long long)__double_as_longlong(res));
+    fallback_site(a, i, rho, u1, u2, e);
   }
 }
 

@@ -66,6 +66,22 @@ __device__ inline int newton64_damped(double u1, double u2, double e, double tol
   return -1;
 }
 
+// The damped FP64 fallback of one site whose first pass missed the
+// tolerance: Newton from the rest start, the solution (or its last iterate)
+// written, status 1 (converged) or 3 (failed), counted in the statistics.
+__device__ inline void fallback_site(const FstarArgs& a, int64_t i, double rho, double u1, double u2, double e) {
+  FS<double> s;
+  double res = 0.0;
+  const int it = newton64_damped(u1, u2, e, a.tol, 200, s, res);
+  if (it >= 0 && a.polish) res = polish_once(s, u1, u2, e);
+  write_mu(a, i, rho, s);
+  if (a.status) a.status[i] = it >= 0 ? 1 : 3;
+  FstarStats& S = stat_slot(a.stats);
+  atomicAdd(&S.fallback, 1ull);
+  if (it < 0) atomicAdd(&S.failed, 1ull);
+  else atomicMax(&S.maxres_bits, (unsigned long long)__double_as_longlong(res));
+}
+
 // Statistics are accumulated per thread over its sites, reduced per
 // wavefront with shuffles and per block in LDS, and added to the global
 // counters once per block (the grid is capped so that these atomics stay few).

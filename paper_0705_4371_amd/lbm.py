@@ -83,6 +83,8 @@ SIGNATURES = {
     "lbm_fstar_set_tolerance": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, C.c_int32]),
     "lbm_fstar_solve": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P, _P, C.POINTER(lbm_solve_stats)]),
     "lbm_fstar_free": (None, [_P]),
+    "lbm_fstar_solve_static": (C.c_int, [_P, C.c_int64, _P, C.c_int32, _P, C.c_double, C.c_double, C.c_int32,
+                                         C.c_int32, _P, _P, C.POINTER(lbm_solve_stats), _P]),
     "lbm_mlp_create": (C.c_int, [C.c_uint64, C.POINTER(_P)]),
     "lbm_mlp_get_params": (C.c_int, [_P, _P]),
     "lbm_mlp_set_params": (C.c_int, [_P, _P]),
@@ -381,6 +383,34 @@ class FstarSolver:
             self.close()
         except Exception:
             pass
+
+
+LBM_FSTAR_STATIC_MLP_MAX = 1 << 20
+LBM_FSTAR_STATIC_MAX_N = 1 << 23
+
+
+def fstar_solve_static(M, start=LBM_START_DEFAULT, net=None, stats=True, mu=None, iters=None, status=None,
+                       tol=1e-10, tol32=2e-6, max32=16, max64=6, stream=None):
+    """lbm_fstar_solve_static (no solver handle, no allocation in the
+    library).  M: cuda float64 [4][n].  Returns (mu, iters, status,
+    stats-or-None)."""
+    import torch
+    assert M.dtype == torch.float64 and M.is_cuda and M.dim() == 2 and M.shape[0] == 4
+    M = M.contiguous()
+    n = M.shape[1]
+    if mu is None:
+        mu = torch.empty_like(M)
+    if iters is None:
+        iters = torch.empty(n, dtype=torch.uint8, device=M.device)
+    if status is None:
+        status = torch.empty(n, dtype=torch.uint8, device=M.device)
+    st = lbm_solve_stats() if stats else None
+    rc = load().lbm_fstar_solve_static(M.data_ptr(), n, mu.data_ptr(), start, net.h if net is not None else None,
+                                       tol, tol32, max32, max64, iters.data_ptr(), status.data_ptr(),
+                                       C.byref(st) if st is not None else None, _stream(stream))
+    if rc not in (LBM_OK, LBM_E_NOCONV):
+        check(rc, "lbm_fstar_solve_static")
+    return mu, iters, status, st
 
 
 class Mlp:
