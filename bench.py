@@ -61,24 +61,79 @@ def host_cpu():
     return {"model": model, "cores_available": cores, "nproc": os.cpu_count()}
 
 
-def cpu_baseline(args):
-    """The oracle (single thread, FP64 C) on a row band of the same shear
-    layer: nx x rows sites, `steps` steps, periodic."""
+def _oracle_rate(oracle, cfg, f, steps, omp):
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = oracle.step(cfg, f, omp=omp)["f"]
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(args, net_params=None):
+    """The oracle (FP64 C) timed on this host: the plain single-threaded
+    build (the parity judge) and the same source built with OpenMP over its
+    site loops, on bounded samples of the workloads (see `sample`)."""
     import numpy as np
     import oracle
     import workloads as W
+    host = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", host["cores_available"]))
+    oracle.build(force=False, omp=True)
+    out = {"unit": "MLUPS", "kind": "oracle", "host": host}
+    # the headline workload: row bands of the shear layer (same nu, delta, k)
     d, rho, u = W.shear_layer(nx=args.cpu_nx, ny=args.cpu_rows, width=80.0 * args.cpu_rows / 4096)
     cfg = oracle.cfg_from_dict(d)
     f = oracle.init(cfg, rho, u)
-    t0 = time.perf_counter()
-    for _ in range(args.cpu_steps):
-        f = oracle.step(cfg, f)["f"]
-    dt = time.perf_counter() - t0
     n = args.cpu_nx * args.cpu_rows
-    return {"value": n * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "host": host_cpu(),
-            "sample": "%d x %d band of the shear layer (same nu, delta, k), %d steps, FP64, %.1f s"
-                      % (args.cpu_nx, args.cpu_rows, args.cpu_steps, dt)}
+    dt_omp = _oracle_rate(oracle, cfg, f, args.cpu_steps, True)
+    d1, rho1, u1 = W.shear_layer(nx=args.cpu_nx, ny=args.cpu_rows // 2, width=80.0 * (args.cpu_rows // 2) / 4096)
+    cfg1 = oracle.cfg_from_dict(d1)
+    f1 = oracle.init(cfg1, rho1, u1)
+    dt1 = _oracle_rate(oracle, cfg1, f1, 2, False)
+    out["value"] = n * args.cpu_steps / dt_omp / 1e6
+    out["cores"] = threads
+    out["sample"] = ("%d x %d band of the 8192 x 4096 shear layer, %d steps, FP64, OpenMP build on %d threads, "
+                     "%.1f s" % (args.cpu_nx, args.cpu_rows, args.cpu_steps, threads, dt_omp))
+    out["single_thread"] = {"value": args.cpu_nx * (args.cpu_rows // 2) * 2 / dt1 / 1e6, "unit": "MLUPS",
+                            "cores": 1, "sample": "%d x %d band, 2 steps, plain build, %.1f s"
+                                                  % (args.cpu_nx, args.cpu_rows // 2, dt1)}
+    # the 1-D shock tube in full (800 sites, 400 steps, FP64)
+    d, rho, u = W.shock_tube()
+    cfg = oracle.cfg_from_dict(d)
+    f = oracle.init(cfg, rho, u[:1])
+    dts = _oracle_rate(oracle, cfg, f, 400, False)
+    out["shock_tube_800"] = {"steps": 400, "seconds": round(dts, 3), "MLUPS": round(800 * 400 / dts / 1e6, 3),
+                             "cores": 1}
+    # the 1200 x 400 square-cylinder channel (Re 1000): a few steps
+    d, rho, u = W.CONFIGS["cylinder_1200x400_re1000"]()
+    cfg = oracle.cfg_from_dict(d)
+    f = oracle.init(cfg, rho, u)
+    dtc = _oracle_rate(oracle, cfg, f, args.cpu_channel_steps, True)
+    mc = 480000 * args.cpu_channel_steps / dtc / 1e6
+    out["channel_1200x400"] = {"steps": args.cpu_channel_steps, "seconds": round(dtc, 3), "MLUPS": round(mc, 3),
+                               "cores": threads, "extrapolated_50k_steps_s": round(50000 * 480000 / (mc * 1e6), 1)}
+    # f*_M of a sample of the 4096 x 2048 moment field to residual 1e-10
+    M = W.moment_field()[:, ::(1 << 23) // args.cpu_fstar_sites][:, :args.cpu_fstar_sites].copy()
+    ns = M.shape[1]
+    fst = {"sites": ns, "cores": threads, "residual": 1e-10}
+    for name, start in (("rest", 0), ("closed_form", 1)):
+        t0 = time.perf_counter()
+        _, it, bad = oracle.fstar_field(M, 1e-10, start, omp=True)
+        dtf = time.perf_counter() - t0
+        fst[name] = {"Msites_per_s": round(ns / dtf / 1e6, 3), "mean_newton_updates": round(float(it.mean()), 3),
+                     "unconverged": bad}
+    if net_params is not None:
+        # the network start in FP64 (forward pass on the oracle), then Newton
+        nm = np.concatenate(W.mlp_norm()).astype(np.float32)
+        t0 = time.perf_counter()
+        y = oracle.mlp_forward(net_params.astype(np.float64), oracle.mlp_features(M, nm))
+        mu = oracle.mlp_unnormalise(y, nm)
+        mu[0] += np.log(M[0])
+        _, it, bad = oracle.fstar_field(M, 1e-10, 2, mu=mu, omp=True)
+        dtf = time.perf_counter() - t0
+        fst["mlp"] = {"Msites_per_s": round(ns / dtf / 1e6, 3), "mean_newton_updates": round(float(it.mean()), 3),
+                      "unconverged": bad, "note": "FP64 forward pass of the trained network on one thread"}
+    out["fstar_4096x2048_sample"] = fst
+    return out
 
 
 def settle(lat, torch, seconds):
@@ -331,9 +386,10 @@ def fstar_leg(args, torch, lbm, W):
         out["cylinder_fstarM"] = cylinder_leg(args, torch, lbm, W, net)
     out["speedup_mlp_vs_rest"] = round(res["rest"]["ms"] / res["mlp"]["ms"], 3)
     out["speedup_closed_form_vs_rest"] = round(res["rest"]["ms"] / res["closed_form"]["ms"], 3)
+    params = net.get_params()
     solver.close()
     net.close()
-    return out
+    return out, params
 
 
 def main():
@@ -351,7 +407,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nx", type=int, default=8192)
     ap.add_argument("--cpu-rows", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-channel-steps", type=int, default=20)
+    ap.add_argument("--cpu-fstar-sites", type=int, default=1 << 16)
     ap.add_argument("--no-fstar", action="store_true", help="skip the f*_M / MLP leg")
     ap.add_argument("--no-active", action="store_true", help="skip the leg with many sites above delta")
     ap.add_argument("--active-rows", type=int, default=256)
@@ -472,12 +530,13 @@ def main():
         out["fp64"] = fp64_leg(args, torch, lbm, W)
     if not args.no_channel:
         out["channel_1200x400"] = channel_leg(args, torch, lbm, W)
+    net_params = None
     if not args.no_fstar:
         print("# f*_M leg", file=sys.stderr, flush=True)
-        out["fstar"] = fstar_leg(args, torch, lbm, W)
+        out["fstar"], net_params = fstar_leg(args, torch, lbm, W)
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args)
+        out["cpu_baseline"] = cpu_baseline(args, net_params)
     print(json.dumps(out), flush=True)
 
 

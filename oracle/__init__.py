@@ -24,6 +24,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP over its site loops: for timing only
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 QE_POLY, QE_ENTROPIC_MM, QE_ENTROPIC_M = 0, 1, 2
 BC_PERIODIC, BC_ZEROGRAD, BC_FREESLIP, BC_INLET_EQ, BC_OUTLET_EQ = 0, 1, 2, 3, 4
@@ -31,15 +33,19 @@ COLL_LBGK, COLL_ELBM = 0, 1
 MLP_NPARAM = 4740
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc into liboracle.so (plain -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+def build(force: bool = True, omp: bool = False) -> str:
+    """Compile oracle.c with gcc into liboracle.so (plain -O2, no fast-math,
+    single-threaded: the judge); with omp=True into liboracle_omp.so with
+    OpenMP over the site loops (the same arithmetic per site; used only to
+    time the oracle on all host cores)."""
+    out = _LIB_OMP if omp else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
-             "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+             "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"] + (["-fopenmp"] if omp else []) + [_SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Cfg(C.Structure):
@@ -59,61 +65,75 @@ class _Info(C.Structure):
 
 
 _lib = None
+_lib_omp = None
 _D = C.POINTER(C.c_double)
 _I64 = C.POINTER(C.c_int64)
 _I32 = C.POINTER(C.c_int32)
 _F32 = C.POINTER(C.c_float)
 
 
-def lib():
-    global _lib
+def lib(omp: bool = False):
+    """The plain oracle library, or (omp=True) its OpenMP timing build."""
+    global _lib, _lib_omp
+    if omp:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+                build(force=True, omp=True)
+            _lib_omp = _declare(C.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        L = C.CDLL(_LIB)
-        L.or_velocities.argtypes = [C.c_int, _I32, _I32, _D]
-        L.or_moments.argtypes = [C.c_int, _D, _D]
-        L.or_qe_poly.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _D]
-        L.or_qe_entropic_mm.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _D]
-        L.or_fstar_feasible.argtypes = [_D]
-        L.or_fstar_newton.argtypes = [_D, C.c_double, C.c_int, _D, _D]
-        L.or_fstar_scalar.argtypes = [_D, _D]
-        L.or_fstar_polish.argtypes = [_D, _D]
-        L.or_fstar_polish.restype = C.c_double
-        L.or_fstar_from_mu.argtypes = [_D, _D]
-        L.or_dft_power.argtypes = [_D, C.c_int64, _D]
-        L.or_dft_power.restype = None
-        L.or_dft_power_at.argtypes = [_D, C.c_int64, C.c_int64]
-        L.or_dft_power_at.restype = C.c_double
-        L.or_delta_S.argtypes = [C.c_int, _D, _D]
-        L.or_delta_S.restype = C.c_longdouble
-        L.or_elbm_alpha.argtypes = [C.c_int, _D, _D]
-        L.or_elbm_alpha.restype = C.c_double
-        L.or_elbm_H.argtypes = [C.c_int, _D, _D, C.c_longdouble]
-        L.or_elbm_H.restype = C.c_longdouble
-        L.or_init.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _D]
-        L.or_step.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _I64, C.POINTER(_Info)]
-        L.or_step_sites.argtypes = [C.POINTER(_Cfg), _D, _I64, C.c_int64, _I64, C.c_int64, _D]
-        L.or_site_dS.argtypes = [C.POINTER(_Cfg), _D, C.c_int64]
-        L.or_site_dS.restype = C.c_double
-        L.or_sums.argtypes = [C.POINTER(_Cfg), _D, _D]
-        L.or_sums.restype = None
-        L.or_mlp_forward.argtypes = [_D, _D, C.c_int64, _D, C.c_int]
-        L.or_mlp_forward.restype = C.c_double
-        L.or_mlp_loss_grad.argtypes = [_D, _D, _D, C.c_int64, _D, C.c_int]
-        L.or_mlp_loss_grad.restype = C.c_double
-        L.or_adam_step.argtypes = [_D, _D, _D, _D, C.c_int64, C.c_int64, C.c_double, C.c_double,
-                                   C.c_double, C.c_double]
-        L.or_bf16_round.argtypes = [C.c_double]
-        L.or_bf16_round.restype = C.c_double
-        L.or_mlp_features.argtypes = [_D, C.c_int64, _F32, _D]
-        L.or_mlp_features.restype = None
-        L.or_mlp_targets.argtypes = [_D, _D, C.c_int64, _F32, _D]
-        L.or_mlp_targets.restype = None
-        L.or_mlp_unnormalise.argtypes = [_D, C.c_int64, _F32, _D]
-        L.or_mlp_unnormalise.restype = None
-        _lib = L
+        _lib = _declare(C.CDLL(_LIB))
     return _lib
+
+
+def _declare(L):
+    """Argument and result types of the exported functions."""
+    L.or_velocities.argtypes = [C.c_int, _I32, _I32, _D]
+    L.or_moments.argtypes = [C.c_int, _D, _D]
+    L.or_qe_poly.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _D]
+    L.or_qe_entropic_mm.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _D]
+    L.or_fstar_feasible.argtypes = [_D]
+    L.or_fstar_newton.argtypes = [_D, C.c_double, C.c_int, _D, _D]
+    L.or_fstar_scalar.argtypes = [_D, _D]
+    L.or_fstar_polish.argtypes = [_D, _D]
+    L.or_fstar_polish.restype = C.c_double
+    L.or_fstar_from_mu.argtypes = [_D, _D]
+    L.or_dft_power.argtypes = [_D, C.c_int64, _D]
+    L.or_dft_power.restype = None
+    L.or_dft_power_at.argtypes = [_D, C.c_int64, C.c_int64]
+    L.or_dft_power_at.restype = C.c_double
+    L.or_delta_S.argtypes = [C.c_int, _D, _D]
+    L.or_delta_S.restype = C.c_longdouble
+    L.or_elbm_alpha.argtypes = [C.c_int, _D, _D]
+    L.or_elbm_alpha.restype = C.c_double
+    L.or_elbm_H.argtypes = [C.c_int, _D, _D, C.c_longdouble]
+    L.or_elbm_H.restype = C.c_longdouble
+    L.or_init.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _D]
+    L.or_step.argtypes = [C.POINTER(_Cfg), _D, _D, _D, _I64, C.POINTER(_Info)]
+    L.or_step_sites.argtypes = [C.POINTER(_Cfg), _D, _I64, C.c_int64, _I64, C.c_int64, _D]
+    L.or_site_dS.argtypes = [C.POINTER(_Cfg), _D, C.c_int64]
+    L.or_site_dS.restype = C.c_double
+    L.or_sums.argtypes = [C.POINTER(_Cfg), _D, _D]
+    L.or_sums.restype = None
+    L.or_mlp_forward.argtypes = [_D, _D, C.c_int64, _D, C.c_int]
+    L.or_mlp_forward.restype = C.c_double
+    L.or_mlp_loss_grad.argtypes = [_D, _D, _D, C.c_int64, _D, C.c_int]
+    L.or_mlp_loss_grad.restype = C.c_double
+    L.or_adam_step.argtypes = [_D, _D, _D, _D, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                               C.c_double, C.c_double]
+    L.or_bf16_round.argtypes = [C.c_double]
+    L.or_bf16_round.restype = C.c_double
+    L.or_mlp_features.argtypes = [_D, C.c_int64, _F32, _D]
+    L.or_mlp_features.restype = None
+    L.or_mlp_targets.argtypes = [_D, _D, C.c_int64, _F32, _D]
+    L.or_mlp_targets.restype = None
+    L.or_mlp_unnormalise.argtypes = [_D, C.c_int64, _F32, _D]
+    L.or_mlp_unnormalise.restype = None
+    L.or_fstar_field.argtypes = [_D, C.c_int64, C.c_double, C.c_int, _D, _I32]
+    L.or_fstar_field.restype = C.c_int64
+    return L
 
 
 def _p(a: np.ndarray):
@@ -172,6 +192,19 @@ def fstar_polish(M, mu):
     mu = np.array(mu, np.float64)
     r = lib().or_fstar_polish(_p(M), _p(mu))
     return mu, float(r)
+
+
+def fstar_field(M, tol=1e-10, start=0, mu=None, omp=False):
+    """Damped-Newton f*_M of a moment field M [4][n] (or_fstar_field): start
+    0 rest, 1 mass-momentum closed form, 2 the multipliers in mu.  Returns
+    (mu [4][n], iterations [n] (negative: infeasible / unconverged), number of
+    unconverged sites)."""
+    M = np.ascontiguousarray(M, np.float64)
+    n = M.shape[1]
+    mu = np.zeros((4, n)) if mu is None else np.ascontiguousarray(mu, np.float64).copy()
+    it = np.zeros(n, np.int32)
+    bad = lib(omp).or_fstar_field(_p(M), n, tol, start, _p(mu), it.ctypes.data_as(_I32))
+    return mu, it, int(bad)
 
 
 def fstar_scalar(M):
@@ -242,17 +275,18 @@ def init(cfg: _Cfg, rho0, u0, twoE0=None) -> np.ndarray:
     return f
 
 
-def step(cfg: _Cfg, f_in: np.ndarray) -> dict:
+def step(cfg: _Cfg, f_in: np.ndarray, omp: bool = False) -> dict:
     """One time step (pre-collision f(t) -> pre-collision f(t+1)).  Returns
-    dict(f, dS, sel, n_above, n_selected, n_invalid, n_fallback, sums)."""
+    dict(f, dS, sel, n_above, n_selected, n_invalid, n_fallback, sums).
+    omp=True runs the OpenMP timing build."""
     f_in = np.ascontiguousarray(f_in, np.float64)
     assert f_in.shape == (cfg.Q, cfg.ny, cfg.nx)
     f_out = np.zeros_like(f_in)
     dS = np.zeros((cfg.ny, cfg.nx))
     sel = np.zeros(max(int(cfg.k), 1), np.int64)
     info = _Info()
-    rc = lib().or_step(C.byref(cfg), _p(f_in), _p(f_out), _p(dS), sel.ctypes.data_as(_I64),
-                       C.byref(info))
+    rc = lib(omp).or_step(C.byref(cfg), _p(f_in), _p(f_out), _p(dS), sel.ctypes.data_as(_I64),
+                          C.byref(info))
     if rc != 0:
         raise MemoryError("oracle step failed (%d)" % rc)
     return dict(f=f_out, dS=dS, sel=sel[:info.n_selected].copy(), n_above=info.n_above,

@@ -230,6 +230,20 @@ static double or_phi(const double* mu, const double* M)
  */
 int or_fstar_newton(const double* M, double tol, int max_iter, double* mu, double* resid)
 {
+  if (!or_fstar_feasible(M)) {
+    *resid = INFINITY;
+    return -1;
+  }
+  mu[0] = log(4.0 * M[0] / 9.0);
+  mu[1] = 0.0;
+  mu[2] = 0.0;
+  mu[3] = -log(4.0);
+  return or_fstar_newton_from(M, tol, max_iter, mu, resid);
+}
+
+/* the same damped Newton from the multipliers in mu on entry */
+int or_fstar_newton_from(const double* M, double tol, int max_iter, double* mu, double* resid)
+{
   *resid = INFINITY;
   if (!or_fstar_feasible(M)) return -1;
   int32_t vx[9], vy[9];
@@ -242,10 +256,6 @@ int or_fstar_newton(const double* M, double tol, int max_iter, double* mu, doubl
     m[i][2] = vy[i];
     m[i][3] = vx[i] * vx[i] + vy[i] * vy[i];
   }
-  mu[0] = log(4.0 * M[0] / 9.0);
-  mu[1] = 0.0;
-  mu[2] = 0.0;
-  mu[3] = -log(4.0);
   for (int it = 0; it <= max_iter; ++it) {
     double fs[9];
     or_fstar_from_mu(mu, fs);
@@ -703,8 +713,12 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS, int6
   }
   memset(info, 0, sizeof(*info));
 
-  /* 1. moments, quasiequilibrium, nonequilibrium entropy */
-  int64_t nc = 0;
+  /* 1. moments, quasiequilibrium, nonequilibrium entropy (the site loops
+     carry OpenMP pragmas for a separate timing build; the plain build runs
+     them in site-index order) */
+  double sums[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t n_fallback = 0, n_invalid = 0;
+#pragma omp parallel for schedule(static) reduction(+ : sums[:4], n_fallback, n_invalid)
   for (int64_t s = 0; s < N; ++s) {
     int64_t x = s % nx, y = s / nx;
     dsl[s] = 0.0L;
@@ -712,11 +726,19 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS, int6
     double f[9], fs[9], M[4];
     for (int i = 0; i < Q; ++i) f[i] = f_in[(int64_t)i * N + s];
     or_moments(Q, f, M);
-    for (int a = 0; a < 4; ++a) info->sums[a] += M[a];
-    info->n_fallback += or_site_qe(c, M, fs);
+    for (int a = 0; a < 4; ++a) sums[a] += M[a];
+    n_fallback += or_site_qe(c, M, fs);
     for (int i = 0; i < Q; ++i) fst[(int64_t)i * N + s] = fs[i];
     dsl[s] = or_delta_S(Q, f, fs);
-    if (isinf(dsl[s])) info->n_invalid++;
+    if (isinf(dsl[s])) n_invalid++;
+  }
+  for (int a = 0; a < 4; ++a) info->sums[a] = sums[a];
+  info->n_fallback = n_fallback;
+  info->n_invalid = n_invalid;
+  /* the candidates C = {s : Delta S(s) > delta}, in site-index order */
+  int64_t nc = 0;
+  for (int64_t s = 0; s < N; ++s) {
+    if (or_solid(c, s % nx, s / nx)) continue;
     if (dsl[s] > (long double)c->delta) {
       cand[nc].dS = dsl[s];
       cand[nc].s = s;
@@ -741,6 +763,7 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS, int6
   info->n_selected = take;
 
   /* 3. collision or Ehrenfests' step */
+#pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
     int64_t x = s % nx, y = s / nx;
     if (or_solid(c, x, y)) {
@@ -760,6 +783,7 @@ int or_step(const or_cfg* c, const double* f_in, double* f_out, double* dS, int6
 
   /* 4. free flight with boundary rules */
   or_post P = {c, fpost, f_in, NULL, 0, beta};
+#pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
     int64_t x = s % nx, y = s / nx;
     for (int i = 0; i < Q; ++i)
@@ -1041,4 +1065,45 @@ void or_sums(const or_cfg* c, const double* f, double* sums)
     for (int a = 0; a < 4; ++a) acc[a] += M[a];
   }
   for (int a = 0; a < 4; ++a) sums[a] = (double)acc[a];
+}
+
+/* ------------------------------------------------------------------------ */
+/* f*_M of a whole moment field (timing of the CPU baseline)                */
+/* ------------------------------------------------------------------------ */
+/*
+ * Solves n sites M [4][n] to the residual tol by the damped Newton above,
+ * from the rest start (start = 0), from the mass-momentum closed form of
+ * Sec. 4.2 (start = 1: mu = (ln(4 rho (2 - s_x)(2 - s_y) / 9), ln X, ln Y,
+ * -ln 4), the multipliers of that formula, since W_i = (4/9) (1/4)^{|v|^2}),
+ * or from the values in mu on entry (start = 2).  iters [n] receives the
+ * Newton updates (-1 infeasible, -2 unconverged).  Returns the number of
+ * sites that did not converge.
+ */
+int64_t or_fstar_field(const double* M, int64_t n, double tol, int start, double* mu, int32_t* iters)
+{
+  int64_t bad = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : bad)
+  for (int64_t s = 0; s < n; ++s) {
+    double m[4] = {M[s], M[n + s], M[2 * n + s], M[3 * n + s]}, x[4] = {0.0, 0.0, 0.0, 0.0}, r;
+    int it;
+    if (start == 0) {
+      it = or_fstar_newton(m, tol, 100, x, &r);
+    } else {
+      if (start == 1) {
+        double u1 = m[1] / m[0], u2 = m[2] / m[0];
+        double sx = sqrt(1.0 + 3.0 * u1 * u1), sy = sqrt(1.0 + 3.0 * u2 * u2);
+        x[0] = log(4.0 * m[0] * (2.0 - sx) * (2.0 - sy) / 9.0);
+        x[1] = log((2.0 * u1 + sx) / (1.0 - u1));
+        x[2] = log((2.0 * u2 + sy) / (1.0 - u2));
+        x[3] = -log(4.0);
+      } else {
+        for (int a = 0; a < 4; ++a) x[a] = mu[a * n + s];
+      }
+      it = or_fstar_newton_from(m, tol, 100, x, &r);
+    }
+    for (int a = 0; a < 4; ++a) mu[a * n + s] = x[a];
+    iters[s] = it;
+    if (it < 0) bad++;
+  }
+  return bad;
 }

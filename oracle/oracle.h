@@ -59,6 +59,9 @@ void or_qe_poly(int Q, double rho, double u1, double u2, double* fs);
 void or_qe_entropic_mm(int Q, double rho, double u1, double u2, double* fs);
 int or_fstar_feasible(const double* M);
 int or_fstar_newton(const double* M, double tol, int max_iter, double* mu, double* resid);
+int or_fstar_newton_from(const double* M, double tol, int max_iter, double* mu, double* resid);
+/* a whole moment field [4][n] (start 0 rest, 1 closed form, 2 mu on entry) */
+int64_t or_fstar_field(const double* M, int64_t n, double tol, int start, double* mu, int32_t* iters);
 int or_fstar_scalar(const double* M, double* mu);
 /* one more Newton update from converged multipliers (kept if the residual does not grow) */
 double or_fstar_polish(const double* M, double* mu);
