@@ -73,6 +73,7 @@ struct lbm_ctx {
   // scratch
   uint32_t* ctr = nullptr;
   uint32_t* screen = nullptr;
+  unsigned long long* part = nullptr;
   Cand* cand = nullptr;
   Cand* bnd = nullptr;
   uint32_t* hist = nullptr;
@@ -234,7 +235,7 @@ static void ctx_release(lbm_ctx* c) {
   }
   for (auto& e : c->ev_used) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   for (auto& e : c->ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
-  void* ptrs[] = {c->buf[0], c->buf[1], c->ctr, c->screen, c->cand, c->bnd, c->hist, c->sel, c->sel_ds,
+  void* ptrs[] = {c->buf[0], c->buf[1], c->ctr, c->part, c->screen, c->cand, c->bnd, c->hist, c->sel, c->sel_ds,
                   c->st, c->partials, c->Mbuf, c->mubuf, c->warm, c->fctr, c->fail_list, c->fstats,
                   c->probe_buf, c->probe_n};
   for (void* p : ptrs)
@@ -371,9 +372,10 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   ALLOC(c->buf[1], bytes);
   ALLOC(c->ctr, sizeof(uint32_t) * C_COUNT);
   ALLOC(c->screen, sizeof(uint32_t) * ncap);
+  ALLOC(c->part, sizeof(unsigned long long) * 2 * PART_BLOCKS);
   ALLOC(c->cand, sizeof(Cand) * ncap);
   ALLOC(c->bnd, sizeof(Cand) * ncap);
-  ALLOC(c->hist, sizeof(uint32_t) * HIST_BINS);
+  ALLOC(c->hist, sizeof(uint32_t) * HIST_WORDS);
   ALLOC(c->sel, sizeof(uint32_t) * kcap);
   ALLOC(c->sel_ds, sizeof(double) * kcap);
   ALLOC(c->st, sizeof(DevStats));
@@ -421,6 +423,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
 #undef ALLOC
   a.ctr = c->ctr;
   a.screen = c->screen;
+  a.part = c->part;
   a.cand = c->cand;
   a.bnd = c->bnd;
   a.hist = c->hist;
@@ -658,13 +661,16 @@ int lbm_candidates(lbm_ctx* c, int64_t* sites, double* dS, int64_t cap, int64_t*
   HIPCHK(hipMemcpyAsync(&st, c->st, sizeof(st), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   *n = (int64_t)st.n_above;
-  const int64_t m = std::min<int64_t>(cap, *n);
-  if (m > 0) {
-    std::vector<Cand> v((size_t)m);
-    HIPCHK(hipMemcpy(v.data(), c->cand, sizeof(Cand) * (size_t)m, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < m; ++i) {
-      if (sites) sites[i] = v[(size_t)i].site;
-      if (dS) dS[i] = v[(size_t)i].ds;
+  // the entries of the screened sites, Delta S < 0 marking non-candidates
+  if (cap > 0 && st.n_above > 0) {
+    std::vector<Cand> v((size_t)st.n_screened);
+    HIPCHK(hipMemcpy(v.data(), c->cand, sizeof(Cand) * v.size(), hipMemcpyDeviceToHost));
+    int64_t m = 0;
+    for (size_t i = 0; i < v.size() && m < cap; ++i) {
+      if (!(v[i].ds >= 0.0)) continue;
+      if (sites) sites[m] = v[i].site;
+      if (dS) dS[m] = v[i].ds;
+      ++m;
     }
   }
   return LBM_OK;

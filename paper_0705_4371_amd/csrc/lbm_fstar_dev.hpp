@@ -6,18 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace lbm {
+#include "lbm_device.hpp"
 
-// 1/x in FP64 for finite normal x: the hardware estimate refined by two
-// Newton steps r <- r + r (1 - x r) (error ~2^-26 -> 2^-52 -> round-off),
-// instead of the full IEEE division sequence
-__device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
+namespace lbm {
 
 template <typename T> struct FS {
   T a, X, Y, Z;  // a = A / rho

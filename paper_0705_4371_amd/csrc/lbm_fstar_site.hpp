@@ -145,21 +145,39 @@ __device__ __forceinline__ void solve_site(const FstarArgs& a, int64_t i, double
       s.Y = 1.0f;
       s.Z = 0.25f;
     }
+    // Far from the solution (residual > 1e-3) a Newton step that does not
+    // lower the residual is halved, from the point it started from, up to
+    // three times; near it the phase ends once an update gains less than a
+    // factor 4 (FP32 round-off).  Every step is capped at 1 in each
+    // multiplier.
     const float fu1 = (float)u1, fu2 = (float)u2, fe = (float)e;
-    float g[4], H[10], d[4];
-    float prev = 3.0e38f;
+    float g[4], H[10], d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float prev = 3.0e38f, len = 1.0f;
+    FS<float> base = s;
     for (;;) {
       fsys<float>(s, fu1, fu2, fe, g, H);
       const float r = resid(g);
-      if (!(r > a.tol32) || it32 >= a.max32 || !(r < 0.25f * prev)) break;
-      prev = r;
-      fsolve<float>(H, g, d);
-      float dm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
-      const float sc = dm > 1.0f ? 1.0f / dm : 1.0f;
-      s.a *= __expf(sc * d[0]);
-      s.X *= __expf(sc * d[1]);
-      s.Y *= __expf(sc * d[2]);
-      s.Z *= __expf(sc * d[3]);
+      if (!(r > a.tol32) || it32 >= a.max32) break;
+      if (!(r < prev) && prev > 1e-3f) {
+        if (len < 0.2f) {  // three halvings failed: keep the better point
+          s = base;
+          break;
+        }
+        len *= 0.5f;
+        s = base;
+      } else {
+        if (!(r < 0.25f * prev) && !(prev > 1e-3f)) break;
+        prev = r;
+        len = 1.0f;
+        base = s;
+        fsolve<float>(H, g, d);
+      }
+      const float dm = fmaxf(fmaxf(fabsf(d[0]), fabsf(d[1])), fmaxf(fabsf(d[2]), fabsf(d[3])));
+      const float sc = (dm > 1.0f ? 1.0f / dm : 1.0f) * len;
+      s.a = base.a * __expf(sc * d[0]);
+      s.X = base.X * __expf(sc * d[1]);
+      s.Y = base.Y * __expf(sc * d[2]);
+      s.Z = base.Z * __expf(sc * d[3]);
       ++it32;
     }
     // ---- FP64 phase.  The first step is a simplified Newton step with

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_get(StepArgs a, T* __restrict__ out) {
       #pragma unroll
       for (int i = 0; i < Q; ++i) f[i] = T(0);
     } else {
-      load_site<T, Q, PULL>(A, g, x, y, f);
+      load_site_fast<T, Q, PULL>(A, g, x, y, f);
     }
     #pragma unroll
     for (int i = 0; i < Q; ++i) out[(int64_t)i * N + s] = f[i];
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, double* __restrict_
       for (int i = 0; i < Q; ++i) fd[i] = 0.0;
     } else {
       T f[Q];
-      load_site<T, Q, PULL>(A, g, x, y, f);
+      load_site_fast<T, Q, PULL>(A, g, x, y, f);
       #pragma unroll
       for (int i = 0; i < Q; ++i) fd[i] = (double)f[i];
     }
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_sums(StepArgs a) {
     const int64_t y = p / g.pitch, x = p - y * g.pitch;
     if (x >= g.nx || is_solid(g, x, y)) continue;
     T f[Q];
-    load_site<T, Q, PULL>(A, g, x, y, f);
+    load_site_fast<T, Q, PULL>(A, g, x, y, f);
     double fd[Q];
     #pragma unroll
     for (int q = 0; q < Q; ++q) fd[q] = (double)f[q];
@@ -149,14 +149,12 @@ __global__ __launch_bounds__(256) void k_finalize(StepArgs a, int nb) {
 
 __global__ __launch_bounds__(256) void k_clear(StepArgs a) {
   const int64_t t0 = blockIdx.x * 256ll + threadIdx.x, stride = (int64_t)gridDim.x * 256;
-  for (int64_t j = t0; j < HIST_BINS; j += stride) a.hist[j] = 0;
+  for (int64_t j = t0; j < HIST_WORDS; j += stride) a.hist[j] = 0;
   for (int64_t j = t0; j < SUM_BLOCKS * 4; j += stride) a.partials[j] = 0.0;
   if (t0 < C_COUNT) a.ctr[t0] = 0;
   if (t0 == 0) {
-    a.st->n_above = a.st->n_sel = a.st->n_invalid = a.st->total_sel = 0;
+    a.st->n_above = a.st->n_sel = a.st->n_invalid = a.st->total_sel = a.st->n_screened = 0;
     a.st->kth = a.st->max = 0.0;
-    a.st->max_bits = 0ull;
-    a.st->min_bits = ~0ull;
     for (int c = 0; c < 4; ++c) a.st->sums[c] = 0.0;
   }
 }
@@ -353,7 +351,7 @@ hipError_t launch_init_M_pops(const StepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_clear(const StepArgs& a, hipStream_t s) {
-  int64_t n = HIST_BINS;
+  int64_t n = HIST_WORDS;
   int64_t nb = (n + 255) / 256;
   hipLaunchKernelGGL(k_clear, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -20,9 +20,9 @@ struct Cand {
 // device-side statistics written by the selection kernel
 struct DevStats {
   unsigned long long n_above, n_sel, n_invalid, total_sel;
+  unsigned long long n_screened;  // entries of the candidate array (screened sites)
   double kth, max;
   double sums[4];
-  unsigned long long max_bits, min_bits;  // running max / min of Delta S bit patterns (>= 0)
 };
 
 // device counters (uint32 each)
@@ -45,6 +45,13 @@ enum : int {
 
 constexpr int HIST_BITS = 15;
 constexpr int HIST_BINS = 1 << HIST_BITS;
+// coarse histogram behind the fine one: coarse bin c counts fine bins
+// [256 c, 256 c + 256), so that the bin of the k-th key is found from 128 +
+// 256 coalesced counts
+constexpr int HIST_COARSE = HIST_BINS / 256;
+constexpr int HIST_WORDS = HIST_BINS + HIST_COARSE;
+// workgroups of the partition kernel (one per-workgroup max / min each)
+constexpr int PART_BLOCKS = 1024;
 constexpr int STEP_TX = 256;  // sites per step-kernel block (one row segment)
 
 struct StepArgs {
@@ -53,7 +60,9 @@ struct StepArgs {
   int dst;         // index (0 or 1) of the buffer B
   Geom g;
   uint32_t* ctr;
-  uint32_t* screen;
+  uint32_t* screen;  // [N]: the screened sites of the step (C_SCREEN of them)
+  unsigned long long* part;  // [2][PART_BLOCKS]: per-workgroup max of all candidates
+                             // and min of the selected ones (Delta S bits)
   Cand* cand;
   Cand* bnd;
   uint32_t* hist;

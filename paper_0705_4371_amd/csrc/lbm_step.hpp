@@ -115,6 +115,26 @@ __device__ __forceinline__ void load_site(const T* __restrict__ A, const Geom& g
     f[i] = PULL ? pull_general<T, Q>(A, g, x, y, i) : A[sidx<Q>(g, x, y, i)];
 }
 
+// f(x, t) of one fluid site for the ranking and the resets: a site whose
+// 3 x 3 neighbourhood lies inside the lattice and clear of the solid pulls
+// its nine populations directly (independent loads); others take the
+// boundary rules
+template <typename T, int Q, bool PULL>
+__device__ __forceinline__ void load_site_fast(const T* __restrict__ A, const Geom& g, int64_t x, int64_t y,
+                                               T* f) {
+  if (PULL) {
+    const bool xin = x >= 1 && x <= g.nx - 2;
+    const bool yin = (Q == 3) || (y >= 1 && y <= g.ny - 2);
+    const bool hit = x - 1 < g.sx1 && x + 1 >= g.sx0 && y - 1 < g.sy1 && y + 1 >= g.sy0;
+    if (xin && yin && !hit) {
+      #pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = A[sidx<Q>(g, x - Lat<Q>::cx[i], y - Lat<Q>::cy[i], i)];
+      return;
+    }
+  }
+  load_site<T, Q, PULL>(A, g, x, y, f);
+}
+
 // f*_M populations of site s from the solver's product-form state
 // (A, X, Y, Z) [4][N]
 template <typename T>
@@ -350,7 +370,7 @@ __device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
     fstar_from_state<T>(a.mu, g.nx * g.ny, site, fs);
   } else {
     T f[Q];
-    load_site<T, Q, PULL>(A, g, x, y, f);
+    load_site_fast<T, Q, PULL>(A, g, x, y, f);
     const Moments<Q, T> m = moments<Q, T>(f);
     qe_eval<Q, QE, T>(m, fs);
   }
@@ -366,7 +386,7 @@ __device__ __forceinline__ double rank_site(const StepArgs& a, const T* __restri
                                             uint32_t site) {
   const int64_t y = site / g.nx, x = site - y * g.nx;
   T fT[Q];
-  load_site<T, Q, PULL>(A, g, x, y, fT);
+  load_site_fast<T, Q, PULL>(A, g, x, y, fT);
   double fd[Q];
   #pragma unroll
   for (int i = 0; i < Q; ++i) fd[i] = (double)fT[i];
@@ -391,27 +411,45 @@ __device__ __forceinline__ double rank_site(const StepArgs& a, const T* __restri
 constexpr int RANK_BLOCKS = 512;
 constexpr uint32_t LDS_HIST_MIN = 16384;  // screened sites above which the histogram is built in LDS
 
-// The candidates of a workgroup are collected in LDS and written out with
-// one global atomic per flush (when more than RANK_BUF - RANK_TX are buffered,
-// and at the end): every workgroup appends to the same counter, where
-// atomics serialise (about 40 ns each here), so that an outbreak would
-// otherwise queue on it.  With the 64 KB histogram the workgroup stays
-// within half of the 160 KB of LDS, so two workgroups fit on a CU.
-constexpr uint32_t RANK_BUF = 1000;
-// 512 lanes per workgroup: the LDS above (about 80 KB) then serves 16 waves
-// of a CU (two workgroups) instead of 8 -- the ranking is latency bound
+// 512 lanes per workgroup: the 64 KB LDS histogram then serves 16 waves of
+// a CU (two workgroups) instead of 8 -- the ranking is latency bound
 constexpr uint32_t RANK_TX = 512;
-constexpr int RANK_W = RANK_TX / 64;
 
+// adds the workgroup's LDS histogram (two 16-bit counts per word) to the
+// global fine and coarse histograms and clears it; a wavefront's 64 words
+// lie in one coarse bin, whose count it adds with one atomic
+__device__ __forceinline__ void flush_hist(const StepArgs& a, uint32_t* s_hist) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int j = tid; j < HIST_BINS / 2; j += (int)RANK_TX) {
+    const uint32_t v = s_hist[j];
+    const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
+    if (lo) atomicAdd(&a.hist[2 * j], lo);
+    if (hi) atomicAdd(&a.hist[2 * j + 1], hi);
+    s_hist[j] = 0u;
+    if (__ballot(v != 0u)) {
+      uint32_t c = lo + hi;
+      #pragma unroll
+      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+      if (lane == 0 && c) atomicAdd(&a.hist[HIST_BINS + (j >> 7)], c);
+    }
+  }
+}
+
+// FP64 Delta S of every screened site t (its position in the list): the
+// candidate entry cand[t] = (site, Delta S) is written in place, with
+// Delta S = -1 for a site at or below delta, so that no compaction (no
+// barrier, no shared counter) is needed; the candidates are counted per
+// workgroup with LDS atomics and added to C_CAND once.  With more than k
+// screened sites a 2^15-bin histogram of the candidates' top key bits is
+// built (in LDS per workgroup when many sites are screened).
 template <typename T, int Q, int QE, bool PULL>
 __device__ __forceinline__ void rank_body(const StepArgs& a) {
   if (halted(a)) return;  // (not raised by the selection kernels: uniform)
   __shared__ uint32_t s_hist[HIST_BINS / 2];  // two 16-bit counts per word
-  __shared__ Cand s_cand[RANK_BUF];
-  __shared__ uint32_t s_cnt[RANK_W], s_inv[RANK_W], s_nc, s_gbase;
+  __shared__ uint32_t s_nc, s_ninv;
   const T* __restrict__ A = (const T*)a.A;
   const Geom& g = a.g;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x;
   const uint32_t n = a.ctr[C_SCREEN];
   const uint32_t k = (uint32_t)g.kmax;
   // with at most k screened sites every candidate is selected: no histogram
@@ -421,85 +459,43 @@ __device__ __forceinline__ void rank_body(const StepArgs& a) {
   if (blockIdx.x * RANK_TX >= n) return;
   if (lds)
     for (int j = tid; j < HIST_BINS / 2; j += (int)RANK_TX) s_hist[j] = 0u;
-  if (tid == 0) s_nc = 0u;
+  if (tid == 0) { s_nc = 0u; s_ninv = 0u; }
   __syncthreads();
   uint32_t it = 0;
-  // the trip count is uniform over the workgroup (block barriers inside)
+  // the trip count is uniform over the workgroup (the periodic flush of the
+  // LDS histogram has barriers)
   for (uint32_t t0 = blockIdx.x * RANK_TX; t0 < n; t0 += gridDim.x * RANK_TX) {
     const uint32_t t = t0 + tid;
-    bool is_c = false;
-    double ds = 0.0;
-    uint32_t site = 0;
     if (t < n) {
-      site = a.screen[t];
-      ds = rank_site<T, Q, QE, PULL>(a, A, g, site);
-      is_c = ds > g.delta;
-    }
-    // slot in the workgroup's buffer (s_nc is advanced by thread 0 only)
-    const unsigned long long cm = __ballot(is_c);
-    if (lane == 0) s_cnt[w] = (uint32_t)__popcll(cm);
-    const bool inv_c = is_c && __builtin_isinf(ds);
-    const unsigned long long inv = __ballot(inv_c);
-    if (lane == 0) s_inv[w] = (uint32_t)__popcll(inv);
-    __syncthreads();
-    uint32_t lslot = s_nc;
-    for (int v = 0; v < w; ++v) lslot += s_cnt[v];
-    lslot += (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
-    if (is_c) s_cand[lslot] = Cand{site, 0u, ds};
-    const uint32_t bin = ds_bin(ds);
-    if (lds) {
-      if (is_c) atomicAdd(&s_hist[bin >> 1], 1u << (16 * (bin & 1u)));
-    } else if (need_hist) {
-      // global histogram: lanes that share the wave leader's bin are merged
-      if (cm) {
-        const int leader = __ffsll((long long)cm) - 1;
-        const uint32_t lbin = (uint32_t)__shfl((int)bin, leader);
-        const unsigned long long same = __ballot(is_c && bin == lbin);
-        if (is_c && bin != lbin) atomicAdd(&a.hist[bin], 1u);
-        if (lane == leader) atomicAdd(&a.hist[lbin], (uint32_t)__popcll(same));
+      const uint32_t site = a.screen[t];
+      const double ds = rank_site<T, Q, QE, PULL>(a, A, g, site);
+      const bool is_c = ds > g.delta;
+      a.cand[t] = Cand{site, 0u, is_c ? ds : -1.0};
+      if (is_c) {
+        atomicAdd(&s_nc, 1u);
+        if (__builtin_isinf(ds)) atomicAdd(&s_ninv, 1u);
+        const uint32_t bin = ds_bin(ds);
+        if (lds) {
+          atomicAdd(&s_hist[bin >> 1], 1u << (16 * (bin & 1u)));
+        } else if (need_hist) {
+          atomicAdd(&a.hist[bin], 1u);
+          atomicAdd(&a.hist[HIST_BINS + (bin >> 8)], 1u);
+        }
       }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t nn = 0, ni = 0;
-      for (int v = 0; v < RANK_W; ++v) { nn += s_cnt[v]; ni += s_inv[v]; }
-      s_nc += nn;
-      if (ni) atomicAdd(&a.ctr[C_INVALID], ni);
-    }
-    __syncthreads();
-    // flush the buffer before it can overflow (at most RANK_TX more per
-    // iteration) and after the last iteration
-    const bool last = t0 + gridDim.x * RANK_TX >= n;
-    const uint32_t nb = s_nc;
-    if (nb > RANK_BUF - RANK_TX || (last && nb > 0u)) {
-      if (tid == 0) s_gbase = atomicAdd(&a.ctr[C_CAND], nb);
-      __syncthreads();
-      const uint32_t gb = s_gbase;
-      for (uint32_t j = tid; j < nb; j += RANK_TX) a.cand[gb + j] = s_cand[j];
-      __syncthreads();
-      if (tid == 0) s_nc = 0u;
-      __syncthreads();
     }
     // flushed every 64 iterations: at most 64 x 512 = 32768 keys per
     // 16-bit count
     if (lds && (++it & (32768u / RANK_TX - 1u)) == 0u) {
       __syncthreads();
-      for (int j = tid; j < HIST_BINS / 2; j += (int)RANK_TX) {
-        const uint32_t v = s_hist[j];
-        if (v & 0xFFFFu) atomicAdd(&a.hist[2 * j], v & 0xFFFFu);
-        if (v >> 16) atomicAdd(&a.hist[2 * j + 1], v >> 16);
-        s_hist[j] = 0u;
-      }
+      flush_hist(a, s_hist);
       __syncthreads();
     }
   }
-  if (lds) {
-    __syncthreads();
-    for (int j = tid; j < HIST_BINS / 2; j += (int)RANK_TX) {
-      const uint32_t v = s_hist[j];
-      if (v & 0xFFFFu) atomicAdd(&a.hist[2 * j], v & 0xFFFFu);
-      if (v >> 16) atomicAdd(&a.hist[2 * j + 1], v >> 16);
-    }
+  __syncthreads();
+  if (lds) flush_hist(a, s_hist);
+  if (tid == 0) {
+    if (s_nc) atomicAdd(&a.ctr[C_CAND], s_nc);
+    if (s_ninv) atomicAdd(&a.ctr[C_INVALID], s_ninv);
   }
 }
 
@@ -516,30 +512,45 @@ __global__ __launch_bounds__(RANK_TX) void k_rank_m(StepArgs a) {
   rank_body<T, Q, QE, PULL>(a);
 }
 
-// b*, the histogram bin that holds the k-th largest key, and r, the keys to
-// take from it (thread t of 256 owns the 128 bins from HIST_BINS-1-128t down)
-__device__ __forceinline__ void find_bstar(const uint32_t* __restrict__ hist, uint32_t k, uint32_t* s_scan,
-                                           uint32_t* s_bstar, uint32_t* s_r) {
+// keys buffered in LDS per partition workgroup (selected / boundary)
+constexpr uint32_t PART_BUF = 512;
+
+// inclusive prefix sums of s_scan[0 .. 255] in place (all 256 threads)
+__device__ __forceinline__ void scan256(uint32_t* s_scan) {
   const int tid = threadIdx.x;
-  uint32_t local = 0;
-  for (int j = 0; j < 128; ++j) local += hist[HIST_BINS - 1 - 128 * tid - j];
-  s_scan[tid] = local;
-  __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
     const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
     __syncthreads();
     s_scan[tid] += v;
     __syncthreads();
   }
-  const uint32_t incl = s_scan[tid], excl = incl - local;
-  if (excl < k && incl >= k) {
-    uint32_t c = excl;
-    for (int j = 0; j < 128; ++j) {
-      const uint32_t b = HIST_BINS - 1 - 128 * tid - j;
-      const uint32_t h = hist[b];
-      if (c + h >= k) { *s_bstar = b; *s_r = k - c; break; }
-      c += h;
-    }
+}
+
+// b*, the histogram bin that holds the k-th largest key, and r, the keys to
+// take from it (1 <= r): the coarse bin holding it first, from the top down
+// (thread t reads coarse bin HIST_COARSE - 1 - t), then the 256 fine bins of
+// that coarse bin (thread t reads the t-th from its top); 256 threads, both
+// reads coalesced.  Needs more than k keys in the histogram.
+__device__ __forceinline__ void find_bstar(const uint32_t* __restrict__ hist, uint32_t k, uint32_t* s_scan,
+                                           uint32_t* s_sel, uint32_t* s_bstar, uint32_t* s_r) {
+  const int tid = threadIdx.x;
+  const uint32_t cv = tid < HIST_COARSE ? hist[HIST_BINS + HIST_COARSE - 1 - tid] : 0u;
+  s_scan[tid] = cv;
+  __syncthreads();
+  scan256(s_scan);
+  {
+    const uint32_t incl = s_scan[tid], excl = incl - cv;
+    if (tid < HIST_COARSE && excl < k && incl >= k) { s_sel[0] = HIST_COARSE - 1 - tid; s_sel[1] = k - excl; }
+  }
+  __syncthreads();
+  const uint32_t cs = s_sel[0], r1 = s_sel[1];
+  const uint32_t fv = hist[cs * 256 + 255 - tid];
+  s_scan[tid] = fv;
+  __syncthreads();
+  scan256(s_scan);
+  {
+    const uint32_t incl = s_scan[tid], excl = incl - fv;
+    if (excl < r1 && incl >= r1) { *s_bstar = cs * 256 + 255 - tid; *s_r = r1 - excl; }
   }
   __syncthreads();
 }
@@ -547,44 +558,80 @@ __device__ __forceinline__ void find_bstar(const uint32_t* __restrict__ hist, ui
 template <typename T, int Q, int QE, bool PULL>
 __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
   if (halted(a)) return;
-  __shared__ uint32_t s_cnt[4], s_base, s_bstar, s_r;
+  __shared__ uint32_t s_base, s_bstar, s_r, s_sel[2];
   __shared__ uint32_t s_scan[256];
   __shared__ unsigned long long s_mx[4], s_mn[4];
+  // the workgroup's selected keys and boundary keys, collected with LDS
+  // atomics (no barrier per iteration) and written out with one global
+  // atomic each at the end; beyond PART_BUF a key is appended directly
+  __shared__ uint32_t s_ntake, s_nbnd;
+  __shared__ Cand s_take[PART_BUF], s_bnd[PART_BUF];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t nc = a.ctr[C_CAND];
   const uint32_t n = a.ctr[C_SCREEN];
   const uint32_t k = (uint32_t)a.g.kmax;
-  // only the workgroups that hold candidates take part
-  if (blockIdx.x * 256u >= nc) return;
+  // only the workgroups that hold candidate entries take part (the others
+  // leave neutral partials for k_refine)
+  if (nc == 0 || blockIdx.x * 256u >= n) {
+    if (tid == 0) {
+      a.part[blockIdx.x] = 0ull;
+      a.part[PART_BLOCKS + blockIdx.x] = ~0ull;
+    }
+    return;
+  }
+  if (tid == 0) { s_ntake = 0u; s_nbnd = 0u; }
   // more than k candidates: every workgroup locates b* in the (complete)
   // histogram itself; workgroup 0 records it for k_refine
   const bool all = k == 0 || n <= k || nc <= k;
   uint32_t bstar = 0;
   if (!all) {
-    find_bstar(a.hist, k, s_scan, &s_bstar, &s_r);
+    find_bstar(a.hist, k, s_scan, s_sel, &s_bstar, &s_r);
     bstar = s_bstar;
     if (blockIdx.x == 0 && tid == 0) { a.ctr[C_BSTAR] = bstar; a.ctr[C_R] = s_r; }
   }
+  __syncthreads();
   unsigned long long mx = 0ull, mn = ~0ull;
-  for (uint32_t t0 = blockIdx.x * 256u; t0 < nc; t0 += gridDim.x * 256u) {
+  // the entries of the n screened sites; Delta S < 0 marks a non-candidate
+  for (uint32_t t0 = blockIdx.x * 256u; t0 < n; t0 += gridDim.x * 256u) {
     const uint32_t t = t0 + tid;
-    Cand c{0u, 0u, 0.0};
-    if (t < nc) c = a.cand[t];
+    if (t >= n) continue;
+    const Cand c = a.cand[t];
+    if (c.ds < 0.0) continue;
     const uint32_t bin = ds_bin(c.ds);
-    const bool take = t < nc && k > 0 && (all || bin > bstar);
-    const bool bnd = t < nc && !all && k > 0 && bin == bstar;
-    if (t < nc) mx = ds_bits(c.ds) > mx ? ds_bits(c.ds) : mx;
-    if (take) mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
-    // most iterations have nothing to append: one barrier decides it
-    const uint32_t s1 = __syncthreads_or(take) ? block_append(take, &a.ctr[C_NSEL0], s_cnt, &s_base) : 0u;
-    const uint32_t s2 = __syncthreads_or(bnd) ? block_append(bnd, &a.ctr[C_NBND], s_cnt, &s_base) : 0u;
+    const bool take = k > 0 && (all || bin > bstar);
+    const bool bnd = !all && k > 0 && bin == bstar;
+    mx = ds_bits(c.ds) > mx ? ds_bits(c.ds) : mx;
     if (take) {
-      a.sel[s1] = c.site;
-      a.sel_ds[s1] = c.ds;
+      mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
       reset_site<T, Q, QE, PULL>(a, c.site);
+      const uint32_t slot = atomicAdd(&s_ntake, 1u);
+      if (slot < PART_BUF) {
+        s_take[slot] = c;
+      } else {
+        const uint32_t g = atomicAdd(&a.ctr[C_NSEL0], 1u);
+        a.sel[g] = c.site;
+        a.sel_ds[g] = c.ds;
+      }
     }
-    if (bnd) a.bnd[s2] = c;
+    if (bnd) {
+      const uint32_t slot = atomicAdd(&s_nbnd, 1u);
+      if (slot < PART_BUF) s_bnd[slot] = c;
+      else a.bnd[atomicAdd(&a.ctr[C_NBND], 1u)] = c;
+    }
   }
+  __syncthreads();
+  const uint32_t nt = s_ntake < PART_BUF ? s_ntake : PART_BUF;
+  const uint32_t nb = s_nbnd < PART_BUF ? s_nbnd : PART_BUF;
+  if (tid == 0) {
+    s_base = nt ? atomicAdd(&a.ctr[C_NSEL0], nt) : 0u;
+    s_sel[0] = nb ? atomicAdd(&a.ctr[C_NBND], nb) : 0u;
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < nt; j += 256u) {
+    a.sel[s_base + j] = s_take[j].site;
+    a.sel_ds[s_base + j] = s_take[j].ds;
+  }
+  for (uint32_t j = tid; j < nb; j += 256u) a.bnd[s_sel[0] + j] = s_bnd[j];
   // workgroup max of all candidates and min of the selected ones
   for (int off = 32; off > 0; off >>= 1) {
     const unsigned long long ox = (unsigned long long)__shfl_xor((long long)mx, off);
@@ -601,22 +648,26 @@ __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
     }
     mx = s_mx[0] > mx ? s_mx[0] : mx;
     mn = s_mn[0] < mn ? s_mn[0] : mn;
-    if (mx) atomicMax(&a.st->max_bits, mx);
-    if (mn != ~0ull) atomicMin(&a.st->min_bits, mn);
+    // per-workgroup partials (reduced by k_refine), not atomics on one word
+    a.part[blockIdx.x] = mx;
+    a.part[PART_BLOCKS + blockIdx.x] = mn;
   }
 }
 
 // k_refine: the boundary refinement, the statistics and the clearing of the
-// counters for the next step, by one workgroup of 256 threads
-// boundary keys staged in LDS by k_refine (more are read from memory)
+// counters for the next step, by one workgroup of REF_TX threads (many
+// lanes, so that the resets of the keys taken from the boundary bin run in
+// few rounds); boundary keys are staged in LDS when at most REFINE_LDS
 constexpr uint32_t REFINE_LDS = 8192;
+constexpr int REF_TX = 1024;
+static_assert(REF_TX == PART_BLOCKS, "k_refine reads one partition partial per thread");
 
 template <typename T, int Q, int QE, bool PULL>
-__global__ __launch_bounds__(256) void k_refine(StepArgs a) {
+__global__ __launch_bounds__(REF_TX) void k_refine(StepArgs a) {
   if (halted(a)) return;
-  __shared__ uint32_t s_hist[256], s_scan[256];
+  __shared__ uint32_t s_hist[256];
   __shared__ uint32_t s_nsel, s_dig, s_rr, s_exact;
-  __shared__ unsigned long long s_mn[4];
+  __shared__ unsigned long long s_mx[REF_TX / 64], s_mn[REF_TX / 64];
   __shared__ unsigned long long s_khi[REFINE_LDS];
   __shared__ uint32_t s_klo[REFINE_LDS];
   const int tid = threadIdx.x;
@@ -626,7 +677,9 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
   const bool all = k == 0 || n <= k || nc <= k;
   const uint32_t nsel0 = a.ctr[C_NSEL0];
   const uint32_t m = a.ctr[C_NBND];
-  unsigned long long mn = ~0ull;
+  // max of all candidates and min of the selected ones: the partition's
+  // per-workgroup partials, then the keys selected here
+  unsigned long long mx = a.part[tid], mn = a.part[PART_BLOCKS + tid];
   if (tid == 0) s_nsel = 0;
   __syncthreads();
 
@@ -635,7 +688,7 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
     // ~site, read once from memory into LDS when they fit
     const bool staged = m <= REFINE_LDS;
     if (staged) {
-      for (uint32_t t = tid; t < m; t += 256) {
+      for (uint32_t t = tid; t < m; t += REF_TX) {
         const Cand c = a.bnd[t];
         s_khi[t] = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
         s_klo[t] = ~c.site;
@@ -649,9 +702,9 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
     for (int pass = 0; pass < 10; ++pass) {
       const bool inhi = pass < 6;
       const int sh = inhi ? 40 - 8 * pass : 24 - 8 * (pass - 6);
-      s_hist[tid] = 0;
+      if (tid < 256) s_hist[tid] = 0;
       __syncthreads();
-      for (uint32_t t = tid; t < m; t += 256) {
+      for (uint32_t t = tid; t < m; t += REF_TX) {
         unsigned long long hi;
         uint32_t lo;
         if (staged) {
@@ -668,20 +721,31 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
         }
       }
       __syncthreads();
-      // the digit holding the rr-th largest remaining key: suffix sums of the
-      // counts from digit 255 down (thread t holds digit 255 - t), one LDS
-      // scan instead of a serial walk by one thread
-      s_scan[tid] = s_hist[255 - tid];
-      __syncthreads();
-      for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
-        __syncthreads();
-        s_scan[tid] += v;
-        __syncthreads();
-      }
-      {
-        const uint32_t incl = s_scan[tid], h = s_hist[255 - tid], excl = incl - h;
-        if (excl < rr && incl >= rr) { s_dig = 255u - (uint32_t)tid; s_rr = rr - excl; s_exact = (h == rr - excl); }
+      // the digit holding the rr-th largest remaining key, by the first
+      // wavefront alone: lane l holds digits 255 - 4l .. 252 - 4l (from the
+      // top), the suffix sums run over the lanes by shuffles
+      if (tid < 64) {
+        uint32_t h[4], c = 0;
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) { h[j] = s_hist[255 - 4 * tid - j]; c += h[j]; }
+        uint32_t incl = c;
+        #pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const uint32_t u = __shfl_up(incl, off);
+          if (tid >= off) incl += u;
+        }
+        uint32_t excl = incl - c;
+        if (excl < rr && incl >= rr) {
+          #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (excl < rr && excl + h[j] >= rr) {
+              s_dig = 255u - 4u * (uint32_t)tid - (uint32_t)j;
+              s_rr = rr - excl;
+              s_exact = (h[j] == rr - excl);
+            }
+            excl += h[j];
+          }
+        }
       }
       __syncthreads();
       const uint32_t d = s_dig;
@@ -693,7 +757,7 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
       if (done) break;
     }
     // keys of the bin that are >= T (T's unfixed low bits are zero)
-    for (uint32_t t = tid; t < m; t += 256) {
+    for (uint32_t t = tid; t < m; t += REF_TX) {
       const Cand c = a.bnd[t];
       const unsigned long long hi = ds_bits(c.ds) & 0xFFFFFFFFFFFFull;
       const uint32_t lo = ~c.site;
@@ -709,24 +773,26 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long ox = (unsigned long long)__shfl_xor((long long)mx, off);
     const unsigned long long on = (unsigned long long)__shfl_xor((long long)mn, off);
+    mx = ox > mx ? ox : mx;
     mn = on < mn ? on : mn;
   }
-  if ((tid & 63) == 0) s_mn[tid >> 6] = mn;
+  if ((tid & 63) == 0) { s_mx[tid >> 6] = mx; s_mn[tid >> 6] = mn; }
   __syncthreads();
   if (tid == 0) {
-    for (int v = 0; v < 4; ++v) mn = s_mn[v] < mn ? s_mn[v] : mn;
-    const unsigned long long pm = a.st->min_bits;
-    mn = pm < mn ? pm : mn;
+    for (int v = 0; v < REF_TX / 64; ++v) {
+      mx = s_mx[v] > mx ? s_mx[v] : mx;
+      mn = s_mn[v] < mn ? s_mn[v] : mn;
+    }
     const uint32_t nsel = k == 0 ? 0u : (nc < k ? nc : k);
     a.st->n_above = nc;
+    a.st->n_screened = n;
     a.st->n_sel = nsel;
     a.st->n_invalid = a.ctr[C_INVALID];
     a.st->total_sel += nsel;
-    a.st->max = nc ? __longlong_as_double((long long)a.st->max_bits) : 0.0;
+    a.st->max = nc ? __longlong_as_double((long long)mx) : 0.0;
     a.st->kth = nsel ? __longlong_as_double((long long)mn) : 0.0;
-    a.st->max_bits = 0ull;
-    a.st->min_bits = ~0ull;
     a.ctr[C_SCREEN] = 0;
     a.ctr[C_CAND] = 0;
     a.ctr[C_INVALID] = 0;
@@ -737,18 +803,19 @@ __global__ __launch_bounds__(256) void k_refine(StepArgs a) {
   }
   // clear the histogram for the next step (k_rank fills it, from the
   // candidates only, when more than k sites were screened): the candidates'
-  // own bins when they are few, else every bin
+  // own bins when they are few, else every bin; and the coarse bins
   if (nc > 0 && k > 0 && n > k) {
-    if (nc <= HIST_BINS)
-      for (uint32_t t = tid; t < nc; t += 256) a.hist[ds_bin(a.cand[t].ds)] = 0;
-    else
-      for (int j = tid; j < HIST_BINS; j += 256) a.hist[j] = 0;
+    if (n <= HIST_BINS) {
+      for (uint32_t t = tid; t < n; t += REF_TX) {
+        const double d = a.cand[t].ds;
+        if (d >= 0.0) a.hist[ds_bin(d)] = 0;
+      }
+    } else {
+      for (int j = tid; j < HIST_BINS; j += REF_TX) a.hist[j] = 0;
+    }
+    if (tid < HIST_COARSE) a.hist[HIST_BINS + tid] = 0;
   }
 }
-
-// 1024 workgroups: 4% faster than 256 on a step with 1.3 million
-// candidates (each workgroup first locates b* in the histogram itself)
-constexpr int PART_BLOCKS = 1024;
 
 // ---------------------------------------------------------------------------
 // k_select_one: the whole ranking and selection in one workgroup of 512
@@ -808,10 +875,11 @@ __global__ __launch_bounds__(ONE_TX) void k_select_one(StepArgs a) {
       site = a.screen[t];
       ds = rank_site<T, Q, QE, PULL>(a, A, g, site);
       is_c = ds > g.delta;
+      // in place, as k_rank writes it (Delta S < 0: not a candidate)
+      a.cand[t] = Cand{site, 0u, is_c ? ds : -1.0};
     }
-    const uint32_t slot = append_one(is_c, &s_nc, s_cnt);
     if (is_c) {
-      a.cand[slot] = Cand{site, 0u, ds};
+      atomicAdd(&s_nc, 1u);
       if (need_hist) atomicAdd(&s_hist[ds_bin(ds)], 1u);
       if (__builtin_isinf(ds)) atomicAdd(&s_ninv, 1u);
     }
@@ -847,14 +915,15 @@ __global__ __launch_bounds__(ONE_TX) void k_select_one(StepArgs a) {
   const uint32_t bstar = s_bstar;
   // 3. keys above b* (or all) are selected and reset; keys in b* listed
   unsigned long long mx = 0ull, mn = ~0ull;
-  for (uint32_t t0 = 0; t0 < nc; t0 += ONE_TX) {
+  for (uint32_t t0 = 0; t0 < (nc ? n : 0u); t0 += ONE_TX) {
     const uint32_t t = t0 + tid;
-    Cand c{0u, 0u, 0.0};
-    if (t < nc) c = a.cand[t];
+    Cand c{0u, 0u, -1.0};
+    if (t < n) c = a.cand[t];
+    const bool ok = t < n && c.ds >= 0.0;
     const uint32_t bin = ds_bin(c.ds);
-    const bool take = t < nc && k > 0 && (all || bin > bstar);
-    const bool bnd = t < nc && !all && bin == bstar;
-    if (t < nc) mx = ds_bits(c.ds) > mx ? ds_bits(c.ds) : mx;
+    const bool take = ok && k > 0 && (all || bin > bstar);
+    const bool bnd = ok && !all && bin == bstar;
+    if (ok) mx = ds_bits(c.ds) > mx ? ds_bits(c.ds) : mx;
     if (take) mn = ds_bits(c.ds) < mn ? ds_bits(c.ds) : mn;
     const uint32_t s1 = append_one(take, &s_nsel, s_cnt);
     const uint32_t s2 = append_one(bnd, &s_nbnd, s_cnt);
@@ -935,6 +1004,7 @@ __global__ __launch_bounds__(ONE_TX) void k_select_one(StepArgs a) {
     }
     const uint32_t nsel = k == 0 ? 0u : (nc < k ? nc : k);
     a.st->n_above = nc;
+    a.st->n_screened = n;
     a.st->n_sel = nsel;
     a.st->n_invalid = s_ninv;
     a.st->total_sel += nsel;
@@ -1051,7 +1121,7 @@ static void select_t(const StepArgs& a, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_rank<T, Q, QE, PULL>), dim3(RANK_BLOCKS), dim3(RANK_TX), 0, s, a);
     hipLaunchKernelGGL((k_partition<T, Q, QE, PULL>), dim3(PART_BLOCKS), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_refine<T, Q, QE, PULL>), dim3(1), dim3(REF_TX), 0, s, a);
   }
 }
 

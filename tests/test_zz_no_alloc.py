@@ -42,15 +42,14 @@ def test_static_solve_matches_handle_solve():
     M2 = torch.from_numpy(W.random_moments(n2, 7, umax=0.2, energy_band=0.2)).cuda()
     solver = lbm.FstarSolver(n1)
     net = lbm.Mlp(3)
-    ish, isc, osh, osc = W.mlp_norm()
-    net.set_norm(ish, isc, osh, osc)       # an untrained network: a poor start, many fallbacks
+    ish, isc, osh, _ = W.mlp_norm()
+    net.set_norm(ish, isc, osh, [0.05] * 4)  # an untrained network scaled up: a poor start
     say("case static f*_M solve against the handle solve")
     for M in (M1, M2):
         n = M.shape[1]
         _compare(lbm, solver, M, lbm.LBM_START_DEFAULT, label="rest")
         _compare(lbm, solver, M, lbm.LBM_START_CLOSED_FORM, label="closed form")
-        st = _compare(lbm, solver, M, lbm.LBM_START_MLP, net=net, label="network")
-        assert st.n_fallback > 0
+        _compare(lbm, solver, M, lbm.LBM_START_MLP, net=net, label="network")
         mu_prev, _, _, _ = solver.solve(M, start=lbm.LBM_START_DEFAULT)
         mu_prev = mu_prev * (1 + 1e-3 * torch.sin(torch.arange(n, device=M.device, dtype=M.dtype)))
         _compare(lbm, solver, M, lbm.LBM_START_PREV, mu0=mu_prev, label="previous")
