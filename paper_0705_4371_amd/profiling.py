@@ -26,8 +26,8 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-STEP_SOURCES = ("lbm_kernels.hip", "lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar.hpp", "lbm_fstar_dev.hpp",
-                "lbm_fstar_site.hpp")
+STEP_SOURCES = ("lbm_step.hpp", "lbm_step_f32q9.hip", "lbm_step_f64q9.hip", "lbm_device.hpp", "lbm_launch.hpp",
+                "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_fstar_site.hpp")
 
 
 def kernel_source_hash() -> str:
