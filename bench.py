@@ -338,14 +338,9 @@ def fstar_leg(args, torch, lbm, W):
     solver = lbm.FstarSolver(max(npairs, args.fx * args.fy))
     mu_tr, _, _, st = solver.solve(Mtr, start=lbm.LBM_START_DEFAULT)
     net = lbm.Mlp(5)
-    ish, isc, osh, osc = W.mlp_norm()
-    net.set_norm(ish, isc, osh, osc)
-    f64 = torch.float64
-    ish_t, isc_t = torch.tensor(ish, dtype=f64, device="cuda"), torch.tensor(isc, dtype=f64, device="cuda")
-    osh_t, osc_t = torch.tensor(osh, dtype=f64, device="cuda"), torch.tensor(osc, dtype=f64, device="cuda")
-    u1, u2, e = Mtr[1] / Mtr[0], Mtr[2] / Mtr[0], Mtr[3] / Mtr[0]
-    X = ((torch.stack([u1, u2, e, u1 * u1 + u2 * u2], 1) - ish_t) * isc_t).float().contiguous()
-    T = ((torch.stack([mu_tr[0] - torch.log(Mtr[0]), mu_tr[1], mu_tr[2], mu_tr[3]], 1) - osh_t) * osc_t).float().contiguous()
+    net.set_norm(*W.mlp_norm())
+    # normalised inputs and targets built by the library (lbm_mlp_pairs)
+    X, T = net.pairs(Mtr, mu_tr)
     del Mtr, mu_tr
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -342,6 +342,13 @@ int lbm_mlp_adam_step(lbm_mlp* net, const float* grad, double lr, void* stream);
 int lbm_mlp_train(lbm_mlp* net, const float* X, const float* T, int64_t n, int32_t epochs,
                   int32_t batch, double lr, uint64_t shuffle_seed, float* loss_per_epoch,
                   void* stream);
+/* Training pairs of the network from moments M and multipliers mu (device
+   double [4][n] each, mu optional): X (device float [n][4]) receives the
+   normalised features (u1, u2, 2E/rho, |u|^2) of M, the inputs that the
+   warm start computes; T (device float [n][4], required with mu) the
+   normalised targets (mu0 - ln rho, mu1, mu2, mu3).  Queued on stream. */
+int lbm_mlp_pairs(const lbm_mlp* net, const double* M, const double* mu, int64_t n, float* X, float* T,
+                  void* stream);
 void lbm_mlp_free(lbm_mlp* net);
 
 /* sizeof(lbm_config) and sizeof(lbm_es_stats) as compiled into the

@@ -242,6 +242,15 @@ int lbm_fstar_solve_static(const double* M, int64_t n, double* mu, int32_t start
 // ---------------------------------------------------------------------------
 // MLP
 // ---------------------------------------------------------------------------
+int lbm_mlp_pairs(const lbm_mlp* net, const double* M, const double* mu, int64_t n, float* X, float* T,
+                  void* stream) {
+  if (!net || !M || !X) return lbm_internal_fail(LBM_E_INVAL, "net, M and X are required");
+  if (mu && !T) return lbm_internal_fail(LBM_E_INVAL, "T is required with mu");
+  if (n < 0) return lbm_internal_fail(LBM_E_INVAL, "n must be >= 0");
+  HIPCHK(launch_mlp_pairs(net->norm, M, mu, n, X, T, (hipStream_t)stream));
+  return LBM_OK;
+}
+
 void lbm_mlp_free(lbm_mlp* net) {
   if (!net) return;
   (void)hipDeviceSynchronize();

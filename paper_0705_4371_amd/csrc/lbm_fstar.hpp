@@ -84,6 +84,9 @@ hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n, fl
 // (mu0 - ln rho, mu1, mu2, mu3) into warm[4][n]
 hipError_t launch_mlp_warm(const float* params, const MlpNorm& nm, const double* M, int64_t n, float* warm,
                            hipStream_t s);
+// training pairs (normalised inputs X, and targets T when mu is given)
+hipError_t launch_mlp_pairs(const MlpNorm& nm, const double* M, const double* mu, int64_t n, float* X, float* T,
+                            hipStream_t s);
 // sample order of a training epoch: position offset + s reads sample
 // perm(offset + s) of the n_total samples (on == 0: identity)
 struct MlpPerm {

@@ -260,6 +260,43 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ p
   }
 }
 
+// training pairs from moments M and multipliers mu ([4][n] each): the
+// network's normalised inputs X [n][4] (the features of k_mlp_forward<WARM>,
+// the same arithmetic) and, when mu is given, its normalised targets T
+// [n][4] = ((mu0 - ln rho, mu1, mu2, mu3) - out_shift) * out_scale
+__global__ __launch_bounds__(256) void k_mlp_pairs(const double* __restrict__ M, const double* __restrict__ mu,
+                                                   MlpNorm nm, int64_t n, float* __restrict__ X,
+                                                   float* __restrict__ T) {
+  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) {
+    const double rho = M[s];
+    const double u1 = M[n + s] / rho, u2 = M[2 * n + s] / rho, e = M[3 * n + s] / rho;
+    const double feat[4] = {u1, u2, e, u1 * u1 + u2 * u2};
+    float4 x;
+    x.x = (float)((feat[0] - nm.in_shift[0]) * nm.in_scale[0]);
+    x.y = (float)((feat[1] - nm.in_shift[1]) * nm.in_scale[1]);
+    x.z = (float)((feat[2] - nm.in_shift[2]) * nm.in_scale[2]);
+    x.w = (float)((feat[3] - nm.in_shift[3]) * nm.in_scale[3]);
+    *(float4*)(X + 4 * s) = x;
+    if (T) {
+      const double tg[4] = {mu[s] - ::log(rho), mu[n + s], mu[2 * n + s], mu[3 * n + s]};
+      float4 t;
+      t.x = (float)((tg[0] - nm.out_shift[0]) * nm.out_scale[0]);
+      t.y = (float)((tg[1] - nm.out_shift[1]) * nm.out_scale[1]);
+      t.z = (float)((tg[2] - nm.out_shift[2]) * nm.out_scale[2]);
+      t.w = (float)((tg[3] - nm.out_shift[3]) * nm.out_scale[3]);
+      *(float4*)(T + 4 * s) = t;
+    }
+  }
+}
+
+hipError_t launch_mlp_pairs(const MlpNorm& nm, const double* M, const double* mu, int64_t n, float* X, float* T,
+                            hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb > 0) hipLaunchKernelGGL(k_mlp_pairs, dim3((unsigned)nb), dim3(256), 0, s, M, mu, nm, n, X, mu ? T : nullptr);
+  return hipGetLastError();
+}
+
 static unsigned fwd_grid(int64_t n) {
   const int64_t tiles = (n + 15) / 16;
   int64_t nb = (tiles + 3) / 4;

@@ -94,6 +94,7 @@ SIGNATURES = {
     "lbm_mlp_loss_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
     "lbm_mlp_adam_step": (C.c_int, [_P, _P, C.c_double, _P]),
     "lbm_mlp_train": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P, _P]),
+    "lbm_mlp_pairs": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
     "lbm_mlp_free": (None, [_P]),
     "lbm_free": (None, [_P]),
     "lbm_strerror": (C.c_char_p, [C.c_int]),
@@ -461,6 +462,20 @@ class Mlp:
 
     def adam_step(self, grad, lr=1e-3, stream=None):
         check(load().lbm_mlp_adam_step(self.h, grad.data_ptr(), lr, _stream(stream)), "lbm_mlp_adam_step")
+
+    def pairs(self, M, mu=None, stream=None):
+        """Normalised network inputs X [n][4] of moments M (cuda float64
+        [4][n]) and, with multipliers mu [4][n], targets T [n][4]
+        (lbm_mlp_pairs).  Returns (X, T or None)."""
+        torch = self.torch
+        M = M.contiguous()
+        n = M.shape[1]
+        X = torch.empty((n, 4), dtype=torch.float32, device=M.device)
+        T = torch.empty((n, 4), dtype=torch.float32, device=M.device) if mu is not None else None
+        check(load().lbm_mlp_pairs(self.h, M.data_ptr(), mu.contiguous().data_ptr() if mu is not None else None, n,
+                                   X.data_ptr(), T.data_ptr() if T is not None else None, _stream(stream)),
+              "lbm_mlp_pairs")
+        return X, T
 
     def train(self, X, T, epochs, batch, lr=1e-3, seed=0, stream=None) -> np.ndarray:
         losses = np.zeros(max(epochs, 1), np.float32)

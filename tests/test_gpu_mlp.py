@@ -111,10 +111,8 @@ def test_training_reduces_loss_and_newton_work():
     norm = W.mlp_norm()
     net.set_norm(*norm)
     nm = net.get_norm()
-    X = oracle.mlp_features(M, nm).astype(np.float32)
-    T = oracle.mlp_targets(M, mu, nm).astype(np.float32)
-    losses = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), epochs=20, batch=4096, lr=3e-3,
-                       seed=5)
+    X, T = net.pairs(torch.from_numpy(M).cuda(), torch.from_numpy(mu).cuda())
+    losses = net.train(X, T, epochs=20, batch=4096, lr=3e-3, seed=5)
     say("  losses", losses[0], losses[-1])
     assert losses[-1] < 0.05 * losses[0]
     Mh = W.random_moments(20000, 104)
@@ -132,4 +130,27 @@ def test_training_reduces_loss_and_newton_work():
     f_ref = np.array([oracle.fstar_from_mu(mu1.cpu().numpy()[:, i]) for i in range(500)])
     assert np.abs(f_net - f_ref).max() < 5e-2 * Mh[0, :500].max()
     s.close()
+    net.close()
+
+
+def test_training_pairs_match_oracle():
+    """lbm_mlp_pairs against the oracle's pinned features and targets: the
+    same FP64 arithmetic rounded to FP32 (within one FP32 rounding: the two
+    compilers may contract |u|^2 differently)."""
+    torch = torch_gpu()
+    import paper_0705_4371_amd.lbm as lbm
+    say("mlp pairs")
+    M, mu = _harvest(torch, 5000, 22)
+    net = lbm.Mlp(1)
+    net.set_norm(*W.mlp_norm())
+    nm = net.get_norm()
+    X, T = net.pairs(torch.from_numpy(M).cuda(), torch.from_numpy(mu).cuda())
+    Xo = oracle.mlp_features(M, nm)
+    To = oracle.mlp_targets(M, mu, nm)
+    Xg, Tg = X.cpu().numpy().astype(np.float64), T.cpu().numpy().astype(np.float64)
+    ulp = lambda v: np.spacing(np.abs(v).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(Xg - Xo) <= ulp(Xo))
+    assert np.all(np.abs(Tg - To) <= ulp(To) + 1e-12 * np.abs(To))
+    X2, T2 = net.pairs(torch.from_numpy(M).cuda())
+    assert T2 is None and torch.equal(X2, X)
     net.close()
