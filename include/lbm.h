@@ -49,11 +49,13 @@ enum { LBM_FP32 = 0, LBM_FP64 = 1 };
 /* boundary rules (Sec. 4.2's channel); west/east accept PERIODIC, ZEROGRAD,
    INLET_EQ (incoming populations = quasiequilibrium of the inlet state),
    OUTLET_EQ (incoming populations = quasiequilibrium at the density and
-   velocity of the new state of the penultimate column; needs nx >= 3 and
-   the solid clear of both columns); south/north accept PERIODIC, ZEROGRAD,
-   FREESLIP (specular reflection).  Corners take the west/east rule. */
+   velocity of the new state of the penultimate column), OUTLET_EQ_PREV (the
+   same at the density and velocity of that column one step earlier: the
+   other reading of Sec. 4.2's outlet; both need nx >= 3 and the solid clear
+   of both columns); south/north accept PERIODIC, ZEROGRAD, FREESLIP
+   (specular reflection).  Corners take the west/east rule. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_ZEROGRAD = 1, LBM_BC_FREESLIP = 2, LBM_BC_INLET_EQ = 3,
-       LBM_BC_OUTLET_EQ = 4 };
+       LBM_BC_OUTLET_EQ = 4, LBM_BC_OUTLET_EQ_PREV = 5 };
 /* collision: LBGK (eq. lbgkLB), f' = f + 2 beta (f* - f); or ELBM
    (eq. elbmLB), f' = f + alpha beta (f* - f) with alpha the nontrivial root
    of S(f + alpha (f* - f)) = S(f) by bisection to 1e-15 (entropic

@@ -28,7 +28,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 QE_POLY, QE_ENTROPIC_MM, QE_ENTROPIC_M = 0, 1, 2
-BC_PERIODIC, BC_ZEROGRAD, BC_FREESLIP, BC_INLET_EQ, BC_OUTLET_EQ = 0, 1, 2, 3, 4
+BC_PERIODIC, BC_ZEROGRAD, BC_FREESLIP, BC_INLET_EQ, BC_OUTLET_EQ, BC_OUTLET_EQ_PREV = 0, 1, 2, 3, 4, 5
 COLL_LBGK, COLL_ELBM = 0, 1
 MLP_NPARAM = 4740
 

@@ -553,7 +553,7 @@ static int or_source(const or_cfg* c, const int32_t* vx, const int32_t* vy, int6
     int b = sx < 0 ? c->bc[0] : c->bc[1];
     if (b == OR_BC_PERIODIC) sx = ((sx % nx) + nx) % nx;
     else if (b == OR_BC_INLET_EQ) return 0;
-    else if (b == OR_BC_OUTLET_EQ) {
+    else if (b == OR_BC_OUTLET_EQ || b == OR_BC_OUTLET_EQ_PREV) {
       *px = sx < 0 ? 1 : nx - 2;
       *py = y;
       *pj = i;
@@ -626,9 +626,14 @@ static double or_new_value(const or_post* P, const int32_t* vx, const int32_t* v
     or_inlet_qe(c, fs);
     return fs[i];
   }
-  /* outlet: density and velocity of the penultimate column at t+1 */
+  /* outlet: density and velocity of the penultimate column, either of its
+     new state at t+1 (OR_BC_OUTLET_EQ) or of its state at t
+     (OR_BC_OUTLET_EQ_PREV; the collision keeps these moments) */
   double g[9], M[4];
-  for (int q = 0; q < c->Q; ++q) g[q] = or_new_value(P, vx, vy, px, py, q);
+  int b = x == 0 ? c->bc[0] : c->bc[1];
+  int64_t N = c->nx * c->ny;
+  for (int q = 0; q < c->Q; ++q)
+    g[q] = b == OR_BC_OUTLET_EQ_PREV ? P->f_in[(int64_t)q * N + py * c->nx + px] : or_new_value(P, vx, vy, px, py, q);
   or_moments(c->Q, g, M);
   double u2 = c->Q == 9 ? M[2] / M[0] : 0.0;
   if (c->qe == OR_QE_POLY) or_qe_poly(c->Q, M[0], M[1] / M[0], u2, fs);

@@ -23,7 +23,8 @@ extern "C" {
 #endif
 
 enum { OR_QE_POLY = 0, OR_QE_ENTROPIC_MM = 1, OR_QE_ENTROPIC_M = 2 };
-enum { OR_BC_PERIODIC = 0, OR_BC_ZEROGRAD = 1, OR_BC_FREESLIP = 2, OR_BC_INLET_EQ = 3, OR_BC_OUTLET_EQ = 4 };
+enum { OR_BC_PERIODIC = 0, OR_BC_ZEROGRAD = 1, OR_BC_FREESLIP = 2, OR_BC_INLET_EQ = 3, OR_BC_OUTLET_EQ = 4,
+       OR_BC_OUTLET_EQ_PREV = 5 };
 enum { OR_COLL_LBGK = 0, OR_COLL_ELBM = 1 };
 
 typedef struct {

@@ -162,7 +162,7 @@ int lbm_validate_config(const lbm_config* c) {
   for (int s = 0; s < 4; ++s) {
     const int b = c->bc[s];
     const bool ok = s < 2 ? (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_INLET_EQ ||
-                             b == LBM_BC_OUTLET_EQ)
+                             b == LBM_BC_OUTLET_EQ || b == LBM_BC_OUTLET_EQ_PREV)
                           : (b == LBM_BC_PERIODIC || b == LBM_BC_ZEROGRAD || b == LBM_BC_FREESLIP);
     if (!ok) return fail(LBM_E_INVAL, "boundary rule %d not allowed on side %d", b, s);
   }
@@ -180,7 +180,8 @@ int lbm_validate_config(const lbm_config* c) {
     if (c->qe == LBM_QE_ENTROPIC_MM && (std::fabs(c->inlet_u[0]) >= 1.0 || std::fabs(c->inlet_u[1]) >= 1.0))
       return fail(LBM_E_INVAL, "entropic inlet state needs |u_j| < 1");
   }
-  const bool out_w = c->bc[0] == LBM_BC_OUTLET_EQ, out_e = c->bc[1] == LBM_BC_OUTLET_EQ;
+  const bool out_w = c->bc[0] == LBM_BC_OUTLET_EQ || c->bc[0] == LBM_BC_OUTLET_EQ_PREV;
+  const bool out_e = c->bc[1] == LBM_BC_OUTLET_EQ || c->bc[1] == LBM_BC_OUTLET_EQ_PREV;
   if ((out_w || out_e) && c->nx < 3) return fail(LBM_E_INVAL, "the outlet rule needs nx >= 3");
   if (c->solid_w < 0 || c->solid_h < 0) return fail(LBM_E_INVAL, "solid size must be >= 0");
   if (c->solid_w > 0 && c->solid_h > 0) {

@@ -47,7 +47,8 @@ template <> struct Lat<3> {
   static __host__ __device__ constexpr double w(int i) { return i == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
 };
 
-enum : int { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_FREESLIP = 2, BC_INLET_EQ = 3, BC_OUTLET_EQ = 4 };
+enum : int { BC_PERIODIC = 0, BC_ZEROGRAD = 1, BC_FREESLIP = 2, BC_INLET_EQ = 3, BC_OUTLET_EQ = 4,
+             BC_OUTLET_EQ_PREV = 5 };
 enum : int { QE_POLY = 0, QE_ENTROPIC_MM = 1, QE_ENTROPIC_M = 2 };
 
 // Geometry and per-step parameters passed by value to every step kernel.

@@ -66,7 +66,7 @@ __device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g
       const int b = sx < 0 ? g.bc[0] : g.bc[1];
       if (b == BC_PERIODIC) sx = sx < 0 ? sx + g.nx : sx - g.nx;
       else if (b == BC_INLET_EQ) return T(g.feq_in[i]);
-      else if (b == BC_OUTLET_EQ) return T(0);
+      else if (b == BC_OUTLET_EQ || b == BC_OUTLET_EQ_PREV) return T(0);
       else { x = sx < 0 ? x + 1 : x - 1; continue; }
     }
     if (sy < 0 || sy >= g.ny) {
@@ -84,13 +84,16 @@ __device__ __forceinline__ T pull_general(const T* __restrict__ A, const Geom& g
 
 // outlet rule of the channel (Sec. 4.2): the populations entering through
 // an outlet face are the quasiequilibrium at the density and velocity of the
-// new state f(xp, y, t) of the penultimate column xp
+// penultimate column xp: of its new state f(xp, y, t) (BC_OUTLET_EQ), or of
+// its state one step earlier (BC_OUTLET_EQ_PREV), read from the
+// post-collision values stored at (xp, y), which carry the same density and
+// momentum
 template <typename T, int Q>
 __device__ __forceinline__ void pull_outlet(const T* __restrict__ A, const Geom& g, int64_t x, int64_t xp,
-                                         int64_t y, T* f) {
+                                         int64_t y, bool prev, T* f) {
   T p[Q], fe[Q];
   #pragma unroll
-  for (int i = 0; i < Q; ++i) p[i] = pull_general<T, Q>(A, g, xp, y, i);
+  for (int i = 0; i < Q; ++i) p[i] = prev ? A[sidx<Q>(g, xp, y, i)] : pull_general<T, Q>(A, g, xp, y, i);
   const Moments<Q, T> m = moments<Q, T>(p);
   const T ux = m.jx / m.rho, uy = m.jy / m.rho;
   if (g.out_qe == QE_POLY) qe_poly<Q, T>(m.rho, ux, uy, fe);
@@ -107,8 +110,14 @@ template <typename T, int Q, bool PULL>
 __device__ __forceinline__ void load_site(const T* __restrict__ A, const Geom& g, int64_t x, int64_t y,
                                           T* f) {
   if (PULL) {
-    if (x == 0 && g.bc[0] == BC_OUTLET_EQ) { pull_outlet<T, Q>(A, g, x, 1, y, f); return; }
-    if (x == g.nx - 1 && g.bc[1] == BC_OUTLET_EQ) { pull_outlet<T, Q>(A, g, x, g.nx - 2, y, f); return; }
+    if (x == 0 && (g.bc[0] == BC_OUTLET_EQ || g.bc[0] == BC_OUTLET_EQ_PREV)) {
+      pull_outlet<T, Q>(A, g, x, 1, y, g.bc[0] == BC_OUTLET_EQ_PREV, f);
+      return;
+    }
+    if (x == g.nx - 1 && (g.bc[1] == BC_OUTLET_EQ || g.bc[1] == BC_OUTLET_EQ_PREV)) {
+      pull_outlet<T, Q>(A, g, x, g.nx - 2, y, g.bc[1] == BC_OUTLET_EQ_PREV, f);
+      return;
+    }
   }
   #pragma unroll
   for (int i = 0; i < Q; ++i)

@@ -21,7 +21,8 @@ LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE, LBM_E_NOCONV, L
 LBM_D1Q3, LBM_D2Q9 = 3, 9
 LBM_QE_POLY, LBM_QE_ENTROPIC_MM, LBM_QE_ENTROPIC_M = 0, 1, 2
 LBM_FP32, LBM_FP64 = 0, 1
-LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ, LBM_BC_OUTLET_EQ = 0, 1, 2, 3, 4
+LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ, LBM_BC_OUTLET_EQ, LBM_BC_OUTLET_EQ_PREV = \
+    0, 1, 2, 3, 4, 5
 LBM_COLL_LBGK, LBM_COLL_ELBM = 0, 1
 LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP, LBM_START_PREV = 0, 1, 2, 3
 LBM_SELECT_AUTO, LBM_SELECT_ONE, LBM_SELECT_MANY = 0, 1, 2
@@ -111,6 +112,9 @@ def load() -> C.CDLL:
         if not os.path.exists(_build.LIB):
             raise RuntimeError("liblbm.so is not built (run __graft_entry__.build()); "
                                "there is no CPU fallback for the GPU path")
+        # torch first: the library then binds to the HIP runtime that torch
+        # loads (torch provides the device memory and streams)
+        import torch  # noqa: F401
         L = C.CDLL(_build.LIB)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -310,7 +314,8 @@ def strouhal(d: dict, rho0, u0, meta: dict, precision: int = LBM_FP32, steps=Non
     at the monitoring point, take the dominant DFT bin k of the final
     meta["window"] (a quarter) of the n recorded samples, St = L (k / n) / u_inf.
     Stops early, with st = None, when the populations become non-finite
-    (checked every `chunk` steps; progress(step, t_max, stats) is called then)."""
+    (checked every `chunk` steps; progress(step, t_max, stats) is called then;
+    last_finite_step is the step number of the state kept by the library)."""
     t_max = int(steps if steps is not None else meta["t_max"])
     n = max(2, int(round(meta["window"] * t_max)))
     # one-workgroup selection: a healthy run has few sites above delta, and
@@ -329,7 +334,9 @@ def strouhal(d: dict, rho0, u0, meta: dict, precision: int = LBM_FP32, steps=Non
                 break
             if progress:
                 progress(done, t_max, st)
-        res = dict(steps=done, finite=finite, n=n, st=None, peak=None, series=None)
+        # after a non-finite step the library keeps the last finite state,
+        # whose step number the statistics report
+        res = dict(steps=done, finite=finite, last_finite_step=st.step, n=n, st=None, peak=None, series=None)
         if finite:
             series = lat.probe_read(n)
             _, peak = dft_power(series[1])

@@ -29,12 +29,14 @@ TOL = {FP64: 1e-12, FP32: 1e-5}
 EPS = 2.0 ** -52
 
 
-@pytest.mark.parametrize("prec,qe", [(FP64, W.QE_ENTROPIC_MM), (FP32, W.QE_ENTROPIC_MM), (FP64, W.QE_POLY)])
-def test_outlet_channel_teacher_forced(prec, qe):
+@pytest.mark.parametrize("prec,qe,outlet", [(FP64, W.QE_ENTROPIC_MM, W.OUTLET_EQ), (FP32, W.QE_ENTROPIC_MM, W.OUTLET_EQ),
+                                            (FP64, W.QE_POLY, W.OUTLET_EQ), (FP64, W.QE_ENTROPIC_MM, W.OUTLET_EQ_PREV),
+                                            (FP32, W.QE_POLY, W.OUTLET_EQ_PREV)])
+def test_outlet_channel_teacher_forced(prec, qe, outlet):
     torch = torch_gpu()
-    d, rho, u, meta = W.cylinder_paper(1000.0, L=4, qe=qe, outlet=W.OUTLET_EQ)
+    d, rho, u, meta = W.cylinder_paper(1000.0, L=4, qe=qe, outlet=outlet)
     d = dict(d, delta=1e-5)
-    say("case outlet channel", d["nx"], d["ny"], "prec", prec, "qe", qe)
+    say("case outlet channel", d["nx"], d["ny"], "prec", prec, "qe", qe, "outlet", outlet)
     lat = lattice(d, prec, rho, u)
     f = perturb(lat.get_populations().double().cpu().numpy(), 21 + prec, 0.03, d["solid"])
     lat.set_populations(torch.from_numpy(f))

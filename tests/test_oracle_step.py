@@ -339,6 +339,23 @@ def test_outlet_rule_matches_numpy_definition(Q):
     stale = oracle.qe_poly(Q, old.sum(), np.dot(vx, old) / old.sum(), 0.0 if Q == 3 else
                            np.dot(oracle.velocities(Q)[1], old) / old.sum())[i]
     assert abs(got[i, 0, 8] - stale) > 1e-6
+    # the other reading (OUTLET_EQ_PREV): the same step, except that every
+    # inward population of the outlet column is the quasiequilibrium of the
+    # old state of column nx - 2, whose density and velocity are typed here
+    # from the moments of that state
+    cp = oracle.make_cfg(Q=Q, nx=9, ny=ny, nu=2e-3, bc=(W.INLET_EQ, oracle.BC_OUTLET_EQ_PREV, W.PERIODIC, W.PERIODIC),
+                         inlet_rho=1.05, inlet_u=(0.04, 0.0))
+    gp = oracle.step(cp, f)["f"]
+    vy = oracle.velocities(Q)[1]
+    for yy in range(ny):
+        old = f[:, yy, 7]
+        r0 = old.sum()
+        fe = oracle.qe_poly(Q, r0, np.dot(vx, old) / r0, 0.0 if Q == 3 else np.dot(vy, old) / r0)
+        for q in np.where(vx < 0)[0]:
+            assert abs(gp[q, yy, 8] - fe[q]) <= 1e-15 * r0
+    inward = np.zeros(gp.shape, bool)
+    inward[vx < 0, :, 8] = True
+    assert np.array_equal(gp[~inward], got[~inward])
 
 
 def test_outlet_corner_and_free_slip():

@@ -15,7 +15,7 @@ import math
 import numpy as np
 
 # boundary-condition codes (same values as the C-ABI and the oracle)
-PERIODIC, ZEROGRAD, FREESLIP, INLET_EQ, OUTLET_EQ = 0, 1, 2, 3, 4
+PERIODIC, ZEROGRAD, FREESLIP, INLET_EQ, OUTLET_EQ, OUTLET_EQ_PREV = 0, 1, 2, 3, 4, 5
 QE_POLY, QE_ENTROPIC_MM, QE_ENTROPIC_M = 0, 1, 2
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
