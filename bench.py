@@ -193,7 +193,7 @@ def cylinder_leg(args, torch, lbm, W, net):
     start and from the trained network start."""
     d, rho, u = W.CONFIGS["cylinder_2400x800_re20000_fstarM"]()
     e0 = W.iso_energy(u[0], u[1])
-    out = {"lattice": "%dx%d" % (d["nx"], d["ny"]), "steps": args.cyl_steps}
+    out = {"lattice": "%dx%d" % (d["nx"], d["ny"]), "steps": max(1, args.cyl_steps // 100) * min(100, max(1, args.cyl_steps))}
     for name, start in (("rest", lbm.LBM_START_DEFAULT), ("mlp", lbm.LBM_START_MLP),
                         ("previous_step", lbm.LBM_START_PREV)):
         cfg = lbm.config_from_workload(d, lbm.LBM_FP32, fstar_start=start,
@@ -208,8 +208,9 @@ def cylinder_leg(args, torch, lbm, W, net):
         above = 0
         failed = 0
         maxres = 0.0
-        chunk = 100
-        for _ in range(args.cyl_steps // chunk):
+        chunk = min(100, max(1, args.cyl_steps))
+        nch = max(1, args.cyl_steps // chunk)
+        for _ in range(nch):
             lat.step(chunk)
             st, _, _ = lat.stats()
             fb += st.n_fallback
@@ -221,11 +222,11 @@ def cylinder_leg(args, torch, lbm, W, net):
         dt = time.perf_counter() - t0
         st, _, ds = lat.stats(sel_cap=256)
         fluid = d["nx"] * d["ny"] - d["solid"][2] * d["solid"][3]
-        out[name] = {"MLUPS": round(fluid * args.cyl_steps / dt / 1e6, 1),
-                     "ms_per_step": round(dt * 1e3 / args.cyl_steps, 4),
+        out[name] = {"MLUPS": round(fluid * nch * chunk / dt / 1e6, 1),
+                     "ms_per_step": round(dt * 1e3 / (nch * chunk), 4),
                      "fallback_sites_sampled_steps": int(fb),
-                     "fallback_rate": fb / (fluid * (args.cyl_steps // chunk)),
-                     "newton_updates_per_site": upd / (fluid * (args.cyl_steps // chunk)),
+                     "fallback_rate": fb / (fluid * nch),
+                     "newton_updates_per_site": upd / (fluid * nch),
                      "failed_sites_sampled_steps": int(failed), "max_residual_sampled_steps": maxres,
                      "last_step": {"n_above_delta": st.n_above_delta, "n_selected": st.n_selected,
                                    "max_dS": st.max_dS, "kth_dS": st.kth_dS, "nonfinite": st.nonfinite},
@@ -324,35 +325,50 @@ def active_leg(args, torch, lbm, lat, n_sites):
                     "is not timed" % chunk}
 
 
-def fstar_leg(args, torch, lbm, W):
-    """Entropic f*_M solve on the 4096 x 2048 moment field: the warm-start MLP
-    is trained on 2^24 (moments, multipliers) pairs produced by the solver
-    (batch 65536, 20 epochs, Adam 1e-3), then the solve is timed from the rest
-    start, the closed-form start and the network start, each to a residual
-    <= 1e-10 (plain Newton fallback enabled)."""
-    import numpy as np
-    out = {}
-    # training pairs: moments of the study's distribution, multipliers by the solver
+def _train_net(args, torch, lbm, W, solver, wide):
+    """A warm-start network trained on 2^pairs_log2 (moments, multipliers)
+    pairs of the study's distribution (wide: |u| <= 0.3, energy +-30%), the
+    multipliers from the solver, the pairs built by the library."""
     npairs = 1 << args.pairs_log2
-    Mtr = torch.from_numpy(W.random_moments(npairs, 5)).cuda()
-    solver = lbm.FstarSolver(max(npairs, args.fx * args.fy))
+    kw = dict(umax=0.3, energy_band=0.3) if wide else {}
+    Mtr = torch.from_numpy(W.random_moments(npairs, 5, **kw)).cuda()
     mu_tr, _, _, st = solver.solve(Mtr, start=lbm.LBM_START_DEFAULT)
     net = lbm.Mlp(5)
-    net.set_norm(*W.mlp_norm())
-    # normalised inputs and targets built by the library (lbm_mlp_pairs)
+    net.set_norm(*W.mlp_norm(wide=wide))
     X, T = net.pairs(Mtr, mu_tr)
     del Mtr, mu_tr
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = net.train(X, T, epochs=args.epochs, batch=args.batch, lr=1e-3, seed=5)
     torch.cuda.synchronize()
-    out["training"] = {"pairs": npairs, "epochs": args.epochs, "batch": args.batch,
-                       "adam_steps": args.epochs * (npairs // args.batch),
-                       "seconds": round(time.perf_counter() - t0, 3),
-                       "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}
+    info = {"pairs": npairs, "epochs": args.epochs, "batch": args.batch,
+            "adam_steps": args.epochs * (npairs // args.batch),
+            "seconds": round(time.perf_counter() - t0, 3),
+            "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}
     del X, T
-    # the timed solves
-    M = torch.from_numpy(W.moment_field(nx=args.fx, ny=args.fy)).cuda()
+    return net, info
+
+
+def _time_gpu(torch, fn, reps=20):
+    """Mean ms of fn() over reps back-to-back calls (HIP events on torch's
+    current stream, which the library's default-stream calls share)."""
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def _solve_starts(torch, lbm, solver, M, net):
+    """Times the f*_M solve of the field M from the rest, closed-form and
+    network starts, the network start's forward alone, and the solve from
+    the exact multipliers (previous-state start at the converged solution:
+    the fixed cost that no start removes)."""
     n = M.shape[1]
     mu = torch.empty_like(M)
     it = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -362,31 +378,65 @@ def fstar_leg(args, torch, lbm, W):
                         ("mlp", lbm.LBM_START_MLP)):
         kw = dict(start=start, net=net if start == lbm.LBM_START_MLP else None, mu=mu, iters=it, status=stt)
         _, _, _, st = solver.solve(M, stats=True, **kw)          # statistics (synchronising)
-        for _ in range(3):
-            solver.solve(M, stats=False, **kw)                    # warm-up
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        reps = 20
-        for _ in range(reps):
-            solver.solve(M, stats=False, **kw)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / reps
+        ms = _time_gpu(torch, lambda: solver.solve(M, stats=False, **kw))
         res[name] = {"ms": round(ms, 4), "Msites_per_s": round(n / ms / 1e3, 1),
                      "mean_newton_updates": round(st.mean_fp32_iters + st.mean_fp64_iters, 4),
                      "mean_fp32": round(st.mean_fp32_iters, 4), "mean_fp64": round(st.mean_fp64_iters, 4),
                      "fallback": int(st.n_fallback), "failed": int(st.n_failed),
                      "max_residual": st.max_resid}
-    out["sites"] = n
-    out["solve"] = res
+    warm = torch.empty((4, n), dtype=torch.float32, device="cuda")
+    res["mlp"]["forward_ms"] = round(_time_gpu(torch, lambda: net.warm_start(M, out=warm)), 4)
+    # exact start: the converged multipliers as the previous-state start
+    solver.solve(M, start=lbm.LBM_START_DEFAULT, stats=False, mu=mu, iters=it, status=stt)
+    kw = dict(start=lbm.LBM_START_PREV, mu=mu, iters=it, status=stt)
+    _, _, _, st = solver.solve(M, stats=True, **kw)
+    ms = _time_gpu(torch, lambda: solver.solve(M, stats=False, **kw))
+    res["exact_start"] = {"ms": round(ms, 4), "mean_fp32": round(st.mean_fp32_iters, 4),
+                          "mean_fp64": round(st.mean_fp64_iters, 4), "failed": int(st.n_failed),
+                          "max_residual": st.max_resid}
+    # HBM floor of each solve: M read (32 B/site), mu written (32 B), the
+    # update count and status bytes (2 B), and the network start read back
+    # (16 B), or the previous multipliers (32 B) for the exact start; the
+    # forward reads M and writes the start (48 B)
+    for name, b in (("rest", 66), ("closed_form", 66), ("mlp", 82), ("exact_start", 98)):
+        res[name]["hbm_bytes_per_site"] = b
+        res[name]["hbm_frac"] = round(b * n / (res[name]["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+    res["mlp"]["forward_hbm_frac"] = round(48 * n / (res["mlp"]["forward_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+    res["speedup_mlp_vs_rest"] = round(res["rest"]["ms"] / res["mlp"]["ms"], 3)
+    res["speedup_closed_form_vs_rest"] = round(res["rest"]["ms"] / res["closed_form"]["ms"], 3)
+    res["speedup_bound_any_start"] = round(res["rest"]["ms"] / res["exact_start"]["ms"], 3)
+    return res
+
+
+def fstar_leg(args, torch, lbm, W):
+    """Entropic f*_M solve on the 4096 x 2048 moment field: the warm-start MLP
+    is trained on 2^24 (moments, multipliers) pairs produced by the solver
+    (batch 65536, 20 epochs, Adam 1e-3), then the solve is timed from the rest
+    start, the closed-form start and the network start, each to a residual
+    <= 1e-10 (plain Newton fallback enabled), beside the network forward
+    alone and the exact start.  The same on a wide field (|u| <= 0.3, energy
+    +-30%) with a network trained on that distribution."""
+    out = {}
+    solver = lbm.FstarSolver(max(1 << args.pairs_log2, args.fx * args.fy))
+    net, out["training"] = _train_net(args, torch, lbm, W, solver, wide=False)
+    M = torch.from_numpy(W.moment_field(nx=args.fx, ny=args.fy)).cuda()
+    out["sites"] = M.shape[1]
+    out["solve"] = _solve_starts(torch, lbm, solver, M, net)
+    del M
     if not args.no_cylinder:
         out["cylinder_fstarM"] = cylinder_leg(args, torch, lbm, W, net)
-    out["speedup_mlp_vs_rest"] = round(res["rest"]["ms"] / res["mlp"]["ms"], 3)
-    out["speedup_closed_form_vs_rest"] = round(res["rest"]["ms"] / res["closed_form"]["ms"], 3)
+    out["speedup_mlp_vs_rest"] = out["solve"]["speedup_mlp_vs_rest"]
+    out["speedup_closed_form_vs_rest"] = out["solve"]["speedup_closed_form_vs_rest"]
     params = net.get_params()
-    solver.close()
     net.close()
+    if not args.no_wide:
+        wnet, winfo = _train_net(args, torch, lbm, W, solver, wide=True)
+        Mw = torch.from_numpy(W.moment_field(nx=args.fx, ny=args.fy, umax=0.3, energy_band=0.3)).cuda()
+        out["wide"] = {"field": "4096x2048 smooth, |u| <= 0.3, 2E/rho within 30% of isothermal",
+                       "training": winfo, "solve": _solve_starts(torch, lbm, solver, Mw, wnet)}
+        del Mw
+        wnet.close()
+    solver.close()
     return out, params
 
 
@@ -413,6 +463,7 @@ def main():
     ap.add_argument("--active-rows", type=int, default=256)
     ap.add_argument("--active-steps", type=int, default=192)
     ap.add_argument("--no-cylinder", action="store_true", help="skip the f*_M cylinder run")
+    ap.add_argument("--no-wide", action="store_true", help="skip the wide-distribution f*_M solves")
     ap.add_argument("--no-channel", action="store_true", help="skip the 1200 x 400 cylinder channel runs")
     ap.add_argument("--channel-steps", type=int, default=50000)
     ap.add_argument("--cyl-steps", type=int, default=2000)

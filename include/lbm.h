@@ -351,6 +351,13 @@ int lbm_mlp_train(lbm_mlp* net, const float* X, const float* T, int64_t n, int32
    normalised targets (mu0 - ln rho, mu1, mu2, mu3).  Queued on stream. */
 int lbm_mlp_pairs(const lbm_mlp* net, const double* M, const double* mu, int64_t n, float* X, float* T,
                   void* stream);
+/* The network start of the f*_M solve (the same kernel as
+   LBM_START_MLP): for moments M (device double [4][n]) writes warm (device
+   float [4][n]) = (mu0 - ln rho, mu1, mu2, mu3), the network output on the
+   features of M, unnormalised.  Queued on stream; n = 0 does nothing (M
+   and warm may then be NULL); LBM_E_INVAL for a NULL net, NULL M or warm
+   with n > 0, or n < 0. */
+int lbm_mlp_warm_start(const lbm_mlp* net, const double* M, int64_t n, float* warm, void* stream);
 void lbm_mlp_free(lbm_mlp* net);
 
 /* sizeof(lbm_config) and sizeof(lbm_es_stats) as compiled into the

@@ -251,6 +251,13 @@ int lbm_mlp_pairs(const lbm_mlp* net, const double* M, const double* mu, int64_t
   return LBM_OK;
 }
 
+int lbm_mlp_warm_start(const lbm_mlp* net, const double* M, int64_t n, float* warm, void* stream) {
+  if (n < 0) return lbm_internal_fail(LBM_E_INVAL, "n must be >= 0");
+  if (!net || (n > 0 && (!M || !warm))) return lbm_internal_fail(LBM_E_INVAL, "net, M and warm are required");
+  if (n > 0) HIPCHK(launch_mlp_warm(net->params, net->norm, M, n, warm, (hipStream_t)stream));
+  return LBM_OK;
+}
+
 void lbm_mlp_free(lbm_mlp* net) {
   if (!net) return;
   (void)hipDeviceSynchronize();

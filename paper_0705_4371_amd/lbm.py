@@ -96,6 +96,7 @@ SIGNATURES = {
     "lbm_mlp_adam_step": (C.c_int, [_P, _P, C.c_double, _P]),
     "lbm_mlp_train": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P, _P]),
     "lbm_mlp_pairs": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
+    "lbm_mlp_warm_start": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "lbm_mlp_free": (None, [_P]),
     "lbm_free": (None, [_P]),
     "lbm_strerror": (C.c_char_p, [C.c_int]),
@@ -483,6 +484,18 @@ class Mlp:
                                    X.data_ptr(), T.data_ptr() if T is not None else None, _stream(stream)),
               "lbm_mlp_pairs")
         return X, T
+
+    def warm_start(self, M, out=None, stream=None):
+        """The solver's network start (mu0 - ln rho, mu1, mu2, mu3) [4][n]
+        (float32; into out when given) for moments M (float64 [4][n] on the
+        device) (lbm_mlp_warm_start)."""
+        M = M.contiguous()
+        n = M.shape[1]
+        warm = out if out is not None else self.torch.empty((4, n), dtype=self.torch.float32, device=M.device)
+        assert warm.shape == (4, n) and warm.dtype == self.torch.float32 and warm.is_contiguous()
+        check(load().lbm_mlp_warm_start(self.h, M.data_ptr(), n, warm.data_ptr(), _stream(stream)),
+              "lbm_mlp_warm_start")
+        return warm
 
     def train(self, X, T, epochs, batch, lr=1e-3, seed=0, stream=None) -> np.ndarray:
         losses = np.zeros(max(epochs, 1), np.float32)

@@ -39,11 +39,6 @@ def noise(seed: int, component: int, n: int) -> np.ndarray:
     return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) * 2.0 - 1.0
 
 
-def beta_of_nu(nu: float) -> float:
-    """LBGK over-relaxation parameter for a kinematic viscosity (c_s^2 = 1/3)."""
-    return 1.0 / (1.0 + 6.0 * nu)
-
-
 # ---------------------------------------------------------------------------
 # Configurations
 # ---------------------------------------------------------------------------
@@ -192,11 +187,15 @@ CONFIGS = {
 }
 
 
-def mlp_norm():
+def mlp_norm(wide: bool = False):
     """Fixed input/output scalings of the warm-start network, sized for the
-    moment distribution above (|u| <= 0.1, energy within 5% of isothermal):
-    features (u1, u2, 2E/rho, |u|^2) and targets (mu0 - ln rho, mu1, mu2, mu3)
-    are mapped to O(1) by x = (value - shift) * scale."""
+    moment distribution above (|u| <= 0.1, energy within 5% of isothermal),
+    or with wide=True for |u| <= 0.3 and energy within 30%: features
+    (u1, u2, 2E/rho, |u|^2) and targets (mu0 - ln rho, mu1, mu2, mu3) are
+    mapped to O(1) by x = (value - shift) * scale."""
+    if wide:
+        return ([0.0, 0.0, 0.7, 0.03], [8.0, 8.0, 8.0, 50.0],
+                [-0.87, 0.0, 0.0, -1.4], [5.0, 2.5, 2.5, 3.3])
     in_shift = [0.0, 0.0, 2.0 / 3.0, 0.005]
     in_scale = [20.0, 20.0, 20.0, 200.0]
     out_shift = [math.log(4.0 / 9.0), 0.0, 0.0, -math.log(4.0)]
