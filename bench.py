@@ -364,7 +364,23 @@ def _time_gpu(torch, fn, reps=20):
     return ev0.elapsed_time(ev1) / reps
 
 
-def _solve_starts(torch, lbm, solver, M, net):
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4  # wave64 vector instructions per second (256 CUs x 4 SIMDs, 4 cycles each)
+
+
+def _fstar_counts():
+    """Vector instruction counts per 64 sites of the solver and network-start
+    kernels on the 4096 x 2048 field, from the committed counter summary,
+    while the hash of those kernels' sources recorded there still matches."""
+    path = os.path.join(ROOT, "profiles", "fstar_kernels_4096x2048_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    from paper_0705_4371_amd.profiling import fstar_source_hash
+    return d["kernels"] if d.get("fstar_source_hash") == fstar_source_hash() else None
+
+
+def _solve_starts(torch, lbm, solver, M, net, counts=None):
     """Times the f*_M solve of the field M from the rest, closed-form and
     network starts, the network start's forward alone, and the solve from
     the exact multipliers (previous-state start at the converged solution:
@@ -402,6 +418,19 @@ def _solve_starts(torch, lbm, solver, M, net):
         res[name]["hbm_bytes_per_site"] = b
         res[name]["hbm_frac"] = round(b * n / (res[name]["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
     res["mlp"]["forward_hbm_frac"] = round(48 * n / (res["mlp"]["forward_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+    # vector issue: counted instructions over the issue slots of the measured time
+    if counts:
+        for name, key, ms in (("rest", "rest", "ms"), ("closed_form", "closed_form", "ms"),
+                              ("exact_start", "exact_start", "ms"), ("mlp", "mlp_forward", "forward_ms")):
+            if key in counts:
+                c = counts[key]
+                frac = c["valu"] * (n / 64.0) / (res[name][ms] * 1e-3) / VALU_ISSUE_PER_S
+                res[name]["forward_issue_frac" if key == "mlp_forward" else "issue_frac"] = round(frac, 4)
+        if "mlp" in counts:
+            solve_ms = res["mlp"]["ms"] - res["mlp"]["forward_ms"]
+            res["mlp"]["issue_frac"] = round(counts["mlp"]["valu"] * (n / 64.0) / (solve_ms * 1e-3)
+                                             / VALU_ISSUE_PER_S, 4)
+        res["issue_counts"] = "profiles/fstar_kernels_4096x2048_pmc.json (instructions per 64 sites)"
     res["speedup_mlp_vs_rest"] = round(res["rest"]["ms"] / res["mlp"]["ms"], 3)
     res["speedup_closed_form_vs_rest"] = round(res["rest"]["ms"] / res["closed_form"]["ms"], 3)
     res["speedup_bound_any_start"] = round(res["rest"]["ms"] / res["exact_start"]["ms"], 3)
@@ -421,7 +450,7 @@ def fstar_leg(args, torch, lbm, W):
     net, out["training"] = _train_net(args, torch, lbm, W, solver, wide=False)
     M = torch.from_numpy(W.moment_field(nx=args.fx, ny=args.fy)).cuda()
     out["sites"] = M.shape[1]
-    out["solve"] = _solve_starts(torch, lbm, solver, M, net)
+    out["solve"] = _solve_starts(torch, lbm, solver, M, net, counts=_fstar_counts())
     del M
     if not args.no_cylinder:
         out["cylinder_fstarM"] = cylinder_leg(args, torch, lbm, W, net)
@@ -455,7 +484,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nx", type=int, default=8192)
     ap.add_argument("--cpu-rows", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--cpu-channel-steps", type=int, default=20)
     ap.add_argument("--cpu-fstar-sites", type=int, default=1 << 16)
     ap.add_argument("--no-fstar", action="store_true", help="skip the f*_M / MLP leg")

@@ -81,7 +81,8 @@ typedef struct lbm_config {
   int32_t qe;         /* LBM_QE_*                                               */
   int32_t precision;  /* LBM_FP32 or LBM_FP64: storage and collision arithmetic */
   int32_t collision;  /* LBM_COLL_*                                             */
-  int64_t nx, ny;     /* lattice size; D1Q3 requires ny == 1; nx >= 2, ny >= 1  */
+  int64_t nx, ny;     /* lattice size; D1Q3 requires ny == 1; 2 <= nx <= 2^25, ny >= 1,
+                         nx * ny < 2^32 - 1 */
   double nu;          /* kinematic viscosity > 0; beta = 1/(1 + 6 nu)           */
   double delta;       /* Ehrenfests' tolerance on Delta S, >= 0 (+inf: off)     */
   int32_t k;          /* at most k Ehrenfests' steps per time step, >= 0        */

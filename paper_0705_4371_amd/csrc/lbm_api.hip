@@ -152,8 +152,8 @@ int lbm_validate_config(const lbm_config* c) {
   if (c->nx < 2 || c->ny < 1) return fail(LBM_E_INVAL, "need nx >= 2 and ny >= 1 (got %lld x %lld)",
                                          (long long)c->nx, (long long)c->ny);
   if (c->lattice == LBM_D1Q3 && c->ny != 1) return fail(LBM_E_INVAL, "D1Q3 requires ny == 1");
-  if (c->nx > (int64_t)1 << 31 || c->ny > (int64_t)1 << 31 || c->nx * c->ny >= (int64_t)0xFFFFFFFFll)
-    return fail(LBM_E_INVAL, "lattice too large: nx * ny must be below 2^32 - 1");
+  if (c->nx > (int64_t)1 << 25 || c->ny > (int64_t)1 << 31 || c->nx * c->ny >= (int64_t)0xFFFFFFFFll)
+    return fail(LBM_E_INVAL, "lattice too large: nx <= 2^25 and nx * ny below 2^32 - 1 are required");
   if (!(c->nu >= 0.0)) return fail(LBM_E_INVAL, "nu must be >= 0 (got %g)", c->nu);
   if (!(c->delta >= 0.0)) return fail(LBM_E_INVAL, "delta must be >= 0 or +inf (got %g)", c->delta);
   if (c->k < 0) return fail(LBM_E_INVAL, "k must be >= 0 (got %d)", c->k);

@@ -75,6 +75,16 @@ __device__ __forceinline__ int64_t sidx(const Geom& g, int64_t x, int64_t y, int
   return ((y * (g.pitch >> 6) + (x >> 6)) * Q + i) * 64 + (x & 63);
 }
 
+// Row-relative addressing of the same layout: a row of tiles holds
+// pitch * Q elements (below 2^32 bytes, since nx <= 2^25), so a site's
+// populations sit at a per-row base (uniform over a workgroup that covers
+// part of one row) plus a 32-bit byte offset per column plus 64 * i elements.
+template <typename T, int Q>
+__device__ __forceinline__ uint32_t col_bytes(int64_t x) {
+  const uint32_t xx = (uint32_t)x;
+  return ((xx >> 6) * (uint32_t)(Q * 64) + (xx & 63u)) * (uint32_t)sizeof(T);
+}
+
 __device__ __forceinline__ bool is_solid(const Geom& g, int64_t x, int64_t y) {
   return x >= g.sx0 && x < g.sx1 && y >= g.sy0 && y < g.sy1;
 }

@@ -136,8 +136,13 @@ __device__ __forceinline__ void load_site_fast(const T* __restrict__ A, const Ge
     const bool yin = (Q == 3) || (y >= 1 && y <= g.ny - 2);
     const bool hit = x - 1 < g.sx1 && x + 1 >= g.sx0 && y - 1 < g.sy1 && y + 1 >= g.sy0;
     if (xin && yin && !hit) {
+      const int64_t rs = g.pitch * Q;
+      const uint32_t oc[3] = {col_bytes<T, Q>(x - 1), col_bytes<T, Q>(x), col_bytes<T, Q>(x + 1)};
       #pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = A[sidx<Q>(g, x - Lat<Q>::cx[i], y - Lat<Q>::cy[i], i)];
+      for (int i = 0; i < Q; ++i) {
+        const char* row = (const char*)(A + (y - Lat<Q>::cy[i]) * rs);
+        f[i] = *(const T*)(row + oc[1 - Lat<Q>::cx[i]] + i * 64 * (int)sizeof(T));
+      }
       return;
     }
   }
@@ -183,8 +188,15 @@ __device__ __forceinline__ void load_segment_site(const T* __restrict__ A, const
     const bool yin = (Q == 3) || (y >= 1 && y <= g.ny - 2);
     const bool hit = x0 - 1 < g.sx1 && x0 + STEP_TX >= g.sx0 && y - 1 < g.sy1 && y + 1 >= g.sy0;
     if (xin && yin && !hit) {
+      // rows y - 1, y, y + 1 at uniform bases, columns x - 1, x, x + 1 at
+      // per-lane 32-bit offsets, population i at a constant 64 i elements
+      const int64_t rs = g.pitch * Q;
+      const uint32_t oc[3] = {col_bytes<T, Q>(x - 1), col_bytes<T, Q>(x), col_bytes<T, Q>(x + 1)};
       #pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = A[sidx<Q>(g, x - Lat<Q>::cx[i], y - Lat<Q>::cy[i], i)];
+      for (int i = 0; i < Q; ++i) {
+        const char* row = (const char*)(A + (y - Lat<Q>::cy[i]) * rs);
+        f[i] = *(const T*)(row + oc[1 - Lat<Q>::cx[i]] + i * 64 * (int)sizeof(T));
+      }
       return;
     }
   }
@@ -239,11 +251,12 @@ __device__ __forceinline__ T collide_store(const StepArgs& a, int64_t x, int64_t
     b2 = T(0.5 * a.g.beta2 * elbm_alpha<Q>(fd, fsd));
   }
   T sum = T(0);
+  char* row = (char*)(B + y * (a.g.pitch * Q)) + col_bytes<T, Q>(x);
   #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const T v = f[i] + b2 * (fs[i] - f[i]);
     sum += v;
-    __builtin_nontemporal_store(v, &B[sidx<Q>(a.g, x, y, i)]);
+    __builtin_nontemporal_store(v, (T*)(row + i * 64 * (int)sizeof(T)));
   }
   return sum;
 }

@@ -9,11 +9,18 @@
   size (the copy's bytes divided by its counter reading), as JSON.  The JSON
   records the hash of the step kernel's sources (``kernel_source_hash``) so
   that a reader can tell when the counters no longer describe the kernel.
+- ``valu``: vector, transcendental, FP64 and matrix-core instruction counts
+  of the f*_M solver and network-start kernels per 64 sites, from counter
+  runs over the 4096 x 2048 moment field, as JSON (with the hash of those
+  kernels' sources).  For each kernel the dispatches are grouped by their
+  exact instruction count (the kernels are deterministic) and the largest
+  group is taken: the field's timed repetitions.
 
 Usage (from the repository root):
   python -m paper_0705_4371_amd.profiling stats DIR --command "..." --title "..."
   python -m paper_0705_4371_amd.profiling pmc --kernel k_step --fetch DIR --write DIR \\
       --copy-fetch DIR --copy-write DIR --algorithmic-bytes B --workload "..." --command "..."
+  python -m paper_0705_4371_amd.profiling valu --dirs DIR [DIR ...] --sites N --command "..."
 """
 from __future__ import annotations
 
@@ -30,13 +37,31 @@ STEP_SOURCES = ("lbm_step.hpp", "lbm_step_f32q9.hip", "lbm_step_f64q9.hip", "lbm
                 "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_fstar_site.hpp")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the sources the fused step kernel is compiled from."""
+FSTAR_SOURCES = ("lbm_fstar.hip", "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_fstar_site.hpp", "lbm_device.hpp",
+                 "lbm_mlp.hip")
+# the solver kernels by start, and the network start
+FSTAR_KERNELS = {"rest": "k_fstar<0>(", "closed_form": "k_fstar<1>(", "mlp": "k_fstar<2>(",
+                 "exact_start": "k_fstar<3>(", "mlp_forward": "k_mlp_warm("}
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU_FMA_F64",
+                 "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_MFMA")
+
+
+def _hash(names) -> str:
     h = hashlib.sha256()
-    for name in STEP_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_0705_4371_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources the fused step kernel is compiled from."""
+    return _hash(STEP_SOURCES)
+
+
+def fstar_source_hash() -> str:
+    """Hash of the sources of the f*_M solver and network-start kernels."""
+    return _hash(FSTAR_SOURCES)
 
 
 def _one(pattern: str) -> str:
@@ -98,6 +123,36 @@ def pmc_summary(a) -> dict:
     }
 
 
+def valu_summary(a) -> dict:
+    per = {}  # dispatch id -> (kernel name, {counter: value})
+    for d in a.dirs:
+        for r in _rows(_one(os.path.join(d, "**", "*counter_collection.csv"))):
+            did = int(r["Dispatch_Id"])
+            name, cnt = per.setdefault(did, (r["Kernel_Name"], {}))
+            if name == r["Kernel_Name"]:
+                cnt[r["Counter_Name"]] = float(r["Counter_Value"])
+    waves = a.sites / 64.0
+    out = {"workload": a.workload, "sites": a.sites, "fstar_source_hash": fstar_source_hash(),
+           "unit": "instructions per wavefront of 64 sites", "commands": a.command, "kernels": {}}
+    for key, match in FSTAR_KERNELS.items():
+        groups = {}
+        for did, (name, cnt) in per.items():
+            if match in name and all(c in cnt for c in VALU_COUNTERS):
+                groups.setdefault(tuple(cnt[c] for c in VALU_COUNTERS), []).append(did)
+        if not groups:
+            continue
+        vals, ids = max(groups.items(), key=lambda kv: len(kv[1]))
+        c = dict(zip(VALU_COUNTERS, vals))
+        out["kernels"][key] = {
+            "kernel": match.rstrip("("), "dispatches": len(ids),
+            "valu": round(c["SQ_INSTS_VALU"] / waves, 1),
+            "transcendental": round((c["SQ_INSTS_VALU_TRANS_F32"] + c["SQ_INSTS_VALU_TRANS_F64"]) / waves, 1),
+            "fp64": round((c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"])
+                          / waves, 1),
+            "mfma": round(c["SQ_INSTS_MFMA"] / waves, 1)}
+    return out
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="what", required=True)
@@ -119,8 +174,17 @@ def main(argv=None) -> None:
     p.add_argument("--workload", required=True)
     p.add_argument("--skip-first", type=int, default=0)
     p.add_argument("--command", action="append", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("--dirs", nargs="+", required=True, help="counter runs (any split of the counters)")
+    v.add_argument("--sites", type=int, default=4096 * 2048)
+    v.add_argument("--workload", default="f*_M moment field 4096x2048 (rho in [0.5, 1.5], |u| <= 0.1, "
+                                          "2E/rho within 5% of isothermal), residual <= 1e-10")
+    v.add_argument("--command", action="append", required=True)
     a = ap.parse_args(argv)
-    if a.what == "stats":
+    if a.what == "valu":
+        json.dump(valu_summary(a), sys.stdout, indent=1)
+        sys.stdout.write("\n")
+    elif a.what == "stats":
         sys.stdout.write(stats_markdown(a.dir, a.command, a.title))
     else:
         json.dump(pmc_summary(a), sys.stdout, indent=1)

@@ -69,6 +69,7 @@ def _bad(L, **kw):
     (dict(solid=(60, 60, 10, 10)), "inside"),
     (dict(bc=(3, 1, 2, 2), inlet_rho=0.0), "inlet"),
     (dict(nx=70000, ny=70000), "too large"),
+    (dict(nx=(1 << 25) + 1, ny=1, lattice=3), "too large"),
     (dict(collision=1), "ELBM needs"),
     (dict(collision=4, qe=1), "collision"),
     (dict(qe=2, lattice=3, ny=1), "D2Q9"),
