@@ -485,11 +485,15 @@ __device__ __forceinline__ void rank_body(const StepArgs& a) {
   __syncthreads();
   uint32_t it = 0;
   // the trip count is uniform over the workgroup (the periodic flush of the
-  // LDS histogram has barriers)
-  for (uint32_t t0 = blockIdx.x * RANK_TX; t0 < n; t0 += gridDim.x * RANK_TX) {
+  // LDS histogram has barriers); the site of the thread's next entry is
+  // loaded one iteration ahead
+  const uint32_t stride = gridDim.x * RANK_TX;
+  uint32_t next = blockIdx.x * RANK_TX + tid < n ? a.screen[blockIdx.x * RANK_TX + tid] : 0u;
+  for (uint32_t t0 = blockIdx.x * RANK_TX; t0 < n; t0 += stride) {
     const uint32_t t = t0 + tid;
+    const uint32_t site = next;
+    if (t + stride < n) next = a.screen[t + stride];
     if (t < n) {
-      const uint32_t site = a.screen[t];
       const double ds = rank_site<T, Q, QE, PULL>(a, A, g, site);
       const bool is_c = ds > g.delta;
       a.cand[t] = Cand{site, 0u, is_c ? ds : -1.0};
@@ -613,11 +617,15 @@ __global__ __launch_bounds__(256) void k_partition(StepArgs a) {
   }
   __syncthreads();
   unsigned long long mx = 0ull, mn = ~0ull;
-  // the entries of the n screened sites; Delta S < 0 marks a non-candidate
-  for (uint32_t t0 = blockIdx.x * 256u; t0 < n; t0 += gridDim.x * 256u) {
-    const uint32_t t = t0 + tid;
-    if (t >= n) continue;
-    const Cand c = a.cand[t];
+  // the entries of the n screened sites; Delta S < 0 marks a non-candidate.
+  // The next entry of the thread is loaded before the current one is
+  // handled, so that its latency overlaps the work (no barrier in the loop)
+  const uint32_t stride = gridDim.x * 256u;
+  uint32_t t = blockIdx.x * 256u + tid;
+  Cand cn = t < n ? a.cand[t] : Cand{0u, 0u, -1.0};
+  for (; t < n; t += stride) {
+    const Cand c = cn;
+    if (t + stride < n) cn = a.cand[t + stride];
     if (c.ds < 0.0) continue;
     const uint32_t bin = ds_bin(c.ds);
     const bool take = k > 0 && (all || bin > bstar);
