@@ -64,7 +64,8 @@ enum { LBM_COLL_LBGK = 0, LBM_COLL_ELBM = 1 };
 /* f*_M Newton start: isothermal rest state at the site density; the
    mass-momentum closed form of Sec. 4.2; the warm-start network; the
    multipliers already held (previous time step / contents of mu) */
-enum { LBM_START_DEFAULT = 0, LBM_START_CLOSED_FORM = 1, LBM_START_MLP = 2, LBM_START_PREV = 3 };
+enum { LBM_START_DEFAULT = 0, LBM_START_CLOSED_FORM = 1, LBM_START_MLP = 2, LBM_START_PREV = 3,
+       LBM_START_PLAIN = 4 };
 /* how the ranking and selection of a step are launched (the result is the
    same): MANY (and AUTO) spread them over many workgroups in three kernels,
    whose cost grows gently with the number of sites above delta; ONE runs
@@ -281,8 +282,12 @@ int lbm_fstar_set_tolerance(lbm_fstar* s, double tol, double tol32, int32_t max3
  * Solves n sites.  M: device double [4][n] (rho, rho u1, rho u2, 2E);
  * mu: device double [4][n] output; start: LBM_START_DEFAULT (isothermal
  * rest state at the site density), LBM_START_CLOSED_FORM (mass-momentum
- * closed form of Sec. 4.2), LBM_START_MLP (network net) or LBM_START_PREV
- * (the values in mu on entry); iters, status:
+ * closed form of Sec. 4.2), LBM_START_MLP (network net), LBM_START_PREV
+ * (the values in mu on entry) or LBM_START_PLAIN (no FP32 phase: plain FP64
+ * Newton with Armijo damping from the rest start at every site, the
+ * method's fallback, up to 200 updates: the reference solve of Sec. 3.3's
+ * Newton that the other starts are compared with; solver only, not a time
+ * step option); iters, status:
  * optional device uint8 [n] (Newton updates; 0 ok, 1 fallback ok,
  * 2 infeasible, 3 failed).  stats (host, optional) synchronises the stream
  * and returns LBM_E_NOCONV if any site failed; without stats the call is

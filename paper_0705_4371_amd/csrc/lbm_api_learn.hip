@@ -147,7 +147,7 @@ int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_
   if (!s || !M || !mu) return lbm_internal_fail(LBM_E_INVAL, "solver, M and mu are required");
   if (n < 0 || n > s->cap) return lbm_internal_fail(LBM_E_INVAL, "n must be in [0, max_n]");
   if (start != LBM_START_DEFAULT && start != LBM_START_CLOSED_FORM && start != LBM_START_MLP &&
-      start != LBM_START_PREV)
+      start != LBM_START_PREV && start != LBM_START_PLAIN)
     return lbm_internal_fail(LBM_E_INVAL, "start must be one of LBM_START_*");
   if (start == LBM_START_MLP && !net) return lbm_internal_fail(LBM_E_INVAL, "LBM_START_MLP needs a network");
   FstarArgs a{};
@@ -167,6 +167,7 @@ int lbm_fstar_solve(lbm_fstar* s, const double* M, int64_t n, double* mu, int32_
   int kind = START_REST;
   if (start == LBM_START_CLOSED_FORM) kind = START_CLOSED;
   if (start == LBM_START_PREV) kind = START_PREV;
+  if (start == LBM_START_PLAIN) kind = START_PLAIN;
   if (start == LBM_START_MLP) {
     kind = START_WARM;
     if (n > 0) HIPCHK(launch_mlp_warm(net->params, net->norm, M, n, s->warm, s->stream));
@@ -191,7 +192,7 @@ int lbm_fstar_solve_static(const double* M, int64_t n, double* mu, int32_t start
     return lbm_internal_fail(LBM_E_INVAL, "n must be in [0, %lld] (got %lld)", (long long)LBM_FSTAR_STATIC_MAX_N,
                              (long long)n);
   if (start != LBM_START_DEFAULT && start != LBM_START_CLOSED_FORM && start != LBM_START_MLP &&
-      start != LBM_START_PREV)
+      start != LBM_START_PREV && start != LBM_START_PLAIN)
     return lbm_internal_fail(LBM_E_INVAL, "start must be one of LBM_START_*");
   if (start == LBM_START_MLP && !net) return lbm_internal_fail(LBM_E_INVAL, "LBM_START_MLP needs a network");
   if (start == LBM_START_MLP && n > LBM_FSTAR_STATIC_MLP_MAX)
@@ -223,6 +224,7 @@ int lbm_fstar_solve_static(const double* M, int64_t n, double* mu, int32_t start
   int kind = START_REST;
   if (start == LBM_START_CLOSED_FORM) kind = START_CLOSED;
   if (start == LBM_START_PREV) kind = START_PREV;
+  if (start == LBM_START_PLAIN) kind = START_PLAIN;
   if (start == LBM_START_MLP) {
     kind = START_WARM;
     if (n > 0) HIPCHK(launch_mlp_warm(net->params, net->norm, M, n, warm, s));

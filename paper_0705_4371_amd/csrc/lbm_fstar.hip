@@ -95,6 +95,7 @@ hipError_t launch_fstar(const FstarArgs& a, int start, hipStream_t s) {
     if (start == START_CLOSED) hipLaunchKernelGGL((k_fstar<START_CLOSED>), dim3(nb), dim3(256), 0, s, a);
     else if (start == START_WARM) hipLaunchKernelGGL((k_fstar<START_WARM>), dim3(nb), dim3(256), 0, s, a);
     else if (start == START_PREV) hipLaunchKernelGGL((k_fstar<START_PREV>), dim3(nb), dim3(256), 0, s, a);
+    else if (start == START_PLAIN) hipLaunchKernelGGL((k_fstar<START_PLAIN>), dim3(nb), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_fstar<START_REST>), dim3(nb), dim3(256), 0, s, a);
   }
   hipLaunchKernelGGL(k_fstar_fallback, dim3(64), dim3(64), 0, s, a);

@@ -7,7 +7,7 @@
 
 namespace lbm {
 
-enum : int { START_REST = 0, START_CLOSED = 1, START_WARM = 2, START_PREV = 3 };
+enum : int { START_REST = 0, START_CLOSED = 1, START_WARM = 2, START_PREV = 3, START_PLAIN = 4 };
 
 struct FstarStats {
   unsigned long long hist[16];   // Newton updates per site (FP32 + FP64 phases)

@@ -116,6 +116,22 @@ __device__ __forceinline__ void solve_site(const FstarArgs& a, int64_t i, double
       if (st) for (int c = 0; c < 4; ++c) st[c] = __builtin_nan("");
     }
     if (a.status) a.status[i] = 2;
+  } else if constexpr (START == START_PLAIN) {
+    // plain FP64 Newton with Armijo damping from the rest start: the
+    // fallback of the method run on every site (the reference solve that
+    // the other starts are measured against)
+    FS<double> t;
+    const int it = newton64_damped(u1, u2, e, a.tol, 200, t, res);
+    if (it >= 0) {
+      it64 = it;
+      write_mu(a, i, rho, t);
+      if (st) { st[0] = t.a * rho; st[1] = t.X; st[2] = t.Y; st[3] = t.Z; }
+      if (a.status) a.status[i] = 0;
+      maxres = fmax(maxres, res);
+    } else {
+      it64 = 200;
+      failed = true;
+    }
   } else {
     // ---- FP32 phase
     FS<float> s;

@@ -13,7 +13,8 @@
 //
 // BF16 rounding points (the CPU oracle's emulation follows them): inputs,
 // weights, hidden activations after SiLU, and back-propagated deltas where
-// they enter a product; biases, bias gradients and SiLU are FP32.
+// they enter a product; biases, bias gradients and SiLU are FP32 (a bias is
+// the initial value of its product's FP32 accumulator).
 #include <hip/hip_runtime.h>
 
 #include "lbm_fstar.hpp"
@@ -164,14 +165,16 @@ __device__ __forceinline__ void tile_sync() {
 template <bool KEEP, int SYNC = SYNC_BLOCK, class Bias = RegBias>
 __device__ __forceinline__ void forward16(const Mats& w, const Bias& bias, bf16x8 xin, __bf16* Hs1, __bf16* Hs2,
                                           int r, int g, f32x4* z1, f32x4* z2, f32x4& y) {
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  // each product starts from its bias (the accumulator's initial value), so
+  // no separate bias addition follows it
   #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 d = mfma(w.w1[t], xin, zero);
+    const f32x4 c = {bias.b1(t, 0), bias.b1(t, 1), bias.b1(t, 2), bias.b1(t, 3)};
+    const f32x4 d = mfma(w.w1[t], xin, c);
     bf16x4 h;
     #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float z = d[j] + bias.b1(t, j);
+      const float z = d[j];
       if (KEEP) z1[t][j] = z;
       h[j] = (__bf16)silu(z);
     }
@@ -183,12 +186,13 @@ __device__ __forceinline__ void forward16(const Mats& w, const Bias& bias, bf16x
   for (int kk = 0; kk < 2; ++kk) b2[kk] = *(const bf16x8*)(Hs1 + r * SROW + 32 * kk + 8 * g);
   #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 d = mfma(w.w2[t][0], b2[0], zero);
+    const f32x4 c = {bias.b2(t, 0), bias.b2(t, 1), bias.b2(t, 2), bias.b2(t, 3)};
+    f32x4 d = mfma(w.w2[t][0], b2[0], c);
     d = mfma(w.w2[t][1], b2[1], d);
     bf16x4 h;
     #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float z = d[j] + bias.b2(t, j);
+      const float z = d[j];
       if (KEEP) z2[t][j] = z;
       h[j] = (__bf16)silu(z);
     }
@@ -198,10 +202,10 @@ __device__ __forceinline__ void forward16(const Mats& w, const Bias& bias, bf16x
   bf16x8 b3[2];
   #pragma unroll
   for (int kk = 0; kk < 2; ++kk) b3[kk] = *(const bf16x8*)(Hs2 + r * SROW + 32 * kk + 8 * g);
-  f32x4 d = mfma(w.w3[0], b3[0], zero);
+  const f32x4 c = {bias.b3(0), bias.b3(1), bias.b3(2), bias.b3(3)};
+  f32x4 d = mfma(w.w3[0], b3[0], c);
   d = mfma(w.w3[1], b3[1], d);
-  #pragma unroll
-  for (int j = 0; j < 4; ++j) y[j] = d[j] + bias.b3(j);
+  y = d;
 }
 
 // ---------------------------------------------------------------------------

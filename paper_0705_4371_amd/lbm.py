@@ -24,7 +24,7 @@ LBM_FP32, LBM_FP64 = 0, 1
 LBM_BC_PERIODIC, LBM_BC_ZEROGRAD, LBM_BC_FREESLIP, LBM_BC_INLET_EQ, LBM_BC_OUTLET_EQ, LBM_BC_OUTLET_EQ_PREV = \
     0, 1, 2, 3, 4, 5
 LBM_COLL_LBGK, LBM_COLL_ELBM = 0, 1
-LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP, LBM_START_PREV = 0, 1, 2, 3
+LBM_START_DEFAULT, LBM_START_CLOSED_FORM, LBM_START_MLP, LBM_START_PREV, LBM_START_PLAIN = 0, 1, 2, 3, 4
 LBM_SELECT_AUTO, LBM_SELECT_ONE, LBM_SELECT_MANY = 0, 1, 2
 
 

@@ -73,6 +73,7 @@ def _bad(L, **kw):
     (dict(collision=1), "ELBM needs"),
     (dict(collision=4, qe=1), "collision"),
     (dict(qe=2, lattice=3, ny=1), "D2Q9"),
+    (dict(qe=2, fstar_start=4), "fstar_start"),
     (dict(bc=(0, 0, 4, 4)), "not allowed"),
     (dict(select_mode=3), "select_mode"),
     (dict(nx=2, ny=4, bc=(3, 4, 2, 2)), "nx >= 3"),
