@@ -19,14 +19,20 @@ ROOT = os.path.dirname(HERE)
 
 SOURCES = ["lbm_step_f32q9.hip", "lbm_fstep_f32.hip", "lbm_step_f64q9.hip", "lbm_fstep_f64.hip",
            "lbm_step_f32q3.hip", "lbm_step_f64q3.hip", "lbm_kernels.hip", "lbm_api.hip", "lbm_fstar.hip",
-           "lbm_mlp.hip", "lbm_api_learn.hip", "lbm_spectrum.hip"]
+           "lbm_mlp.hip", "lbm_mlp_infer.hip", "lbm_api_learn.hip", "lbm_spectrum.hip"]
 HEADERS = ["lbm_device.hpp", "lbm_launch.hpp", "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_internal.hpp",
-           "lbm_fstar_site.hpp", "lbm_step.hpp"]
+           "lbm_fstar_site.hpp", "lbm_step.hpp", "lbm_mlp_dev.hpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions are generated
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-function"]
+
+
+# per translation unit: the inference kernels keep the matrix-core results
+# in ordinary vector registers, so the activations read them without a copy
+# out of the accumulation registers
+EXTRA_FLAGS = {"lbm_mlp_infer.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def hipcc() -> str:
@@ -56,7 +62,7 @@ def _compile(src: str, incremental: bool, verbose: bool) -> str:
         if all(os.path.getmtime(d) <= t for d in [src] + _deps()):
             return obj
     tmp = obj + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-c", src, "-o", tmp]
+    cmd = [hipcc()] + HIPCC_FLAGS + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

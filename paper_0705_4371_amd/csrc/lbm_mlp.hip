@@ -1,377 +1,13 @@
-// lbm_mlp.hip -- the learned warm start of the f*_M solve: an MLP
-// 4 -> 64 -> 64 -> 4 with SiLU, BF16 operands on the gfx950 matrix cores
-// (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; forward, backward
-// (per-block gradient partials, fixed-order reduction) and Adam.
-//
-// Products are formed transposed, out^T = W . act^T, so that the weights are
-// the A operand (held in registers for a whole kernel) and a tile of 16
-// samples is the B operand.  With lane l, r = l % 16, g = l / 16:
-//   A operand: lane holds A[r][8g .. 8g+7]      (16 x 32, row-major K)
-//   B operand: lane holds B[8g .. 8g+7][r]      (32 x 16)
-//   D result : lane holds D[4g .. 4g+3][r]      (16 x 16)
-// Activations move between layers through per-wave LDS tiles.
-//
-// BF16 rounding points (the CPU oracle's emulation follows them): inputs,
-// weights, hidden activations after SiLU, and back-propagated deltas where
-// they enter a product; biases, bias gradients and SiLU are FP32 (a bias is
-// the initial value of its product's FP32 accumulator).
+// lbm_mlp.hip -- training of the learned warm start of the f*_M solve (the
+// MLP 4 -> 64 -> 64 -> 4 with SiLU of lbm_mlp_dev.hpp): forward and
+// backward on BF16 operands of the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16) with FP32 accumulation, per-block gradient
+// partials reduced in fixed order, and Adam.
 #include <hip/hip_runtime.h>
 
-#include "lbm_fstar.hpp"
+#include "lbm_mlp_dev.hpp"
 
 namespace lbm {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// SiLU z sigma(z) and its derivative sigma(z)(1 + z(1 - sigma(z))) in FP32;
-// the hardware reciprocal (1 ulp) is ample: the activation is rounded to
-// BF16 (8 bits) before its next use
-__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
-__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
-__device__ __forceinline__ float dsilu(float z) {
-  const float s = sigm(z);
-  return s * (1.0f + z * (1.0f - s));
-}
-
-__device__ __forceinline__ bf16x8 zero8() {
-  bf16x8 v;
-  #pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
-  return v;
-}
-
-__device__ __forceinline__ bf16x8 load8(const float* p) {
-  bf16x8 v;
-  #pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = (__bf16)p[j];
-  return v;
-}
-
-// weight operands of the three layers for this lane
-struct Mats {
-  bf16x8 w1[4];     // layer 1, unit tile t: W1[16t + r][k], k < 4 real
-  bf16x8 w2[4][2];  // layer 2, unit tile t, k step kk: W2[16t + r][32kk + 8g + j]
-  bf16x8 w3[2];     // layer 3, k step kk: W3[r][32kk + 8g + j], r < 4 real
-};
-struct Weights : Mats {
-  float b1[4][4], b2[4][4];  // bias of unit 16t + 4g + j
-  float b3[4];               // bias of output j (lanes g == 0)
-};
-
-__device__ void load_mats(const float* __restrict__ p, int r, int g, Mats& w) {
-  #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    bf16x8 v = zero8();
-    if (g == 0) {
-      #pragma unroll
-      for (int j = 0; j < 4; ++j) v[j] = (__bf16)p[MLP_OW1 + (16 * t + r) * 4 + j];
-    }
-    w.w1[t] = v;
-    #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) w.w2[t][kk] = load8(p + MLP_OW2 + (16 * t + r) * 64 + 32 * kk + 8 * g);
-  }
-  #pragma unroll
-  for (int kk = 0; kk < 2; ++kk) w.w3[kk] = r < 4 ? load8(p + MLP_OW3 + r * 64 + 32 * kk + 8 * g) : zero8();
-}
-
-__device__ void load_weights(const float* __restrict__ p, int r, int g, Weights& w) {
-  load_mats(p, r, g, w);
-  #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      w.b1[t][j] = p[MLP_OB1 + 16 * t + 4 * g + j];
-      w.b2[t][j] = p[MLP_OB2 + 16 * t + 4 * g + j];
-    }
-  }
-  #pragma unroll
-  for (int j = 0; j < 4; ++j) w.b3[j] = g == 0 ? p[MLP_OB3 + j] : 0.0f;
-}
-
-// bias access for forward16: the lane's registers (training) or a per-block
-// LDS copy (inference, which keeps fewer registers live)
-struct RegBias {
-  const Weights& w;
-  __device__ float b1(int t, int j) const { return w.b1[t][j]; }
-  __device__ float b2(int t, int j) const { return w.b2[t][j]; }
-  __device__ float b3(int j) const { return w.b3[j]; }
-};
-struct LdsBias {
-  const float* p;  // the 4740 parameters' bias entries copied to LDS: b1 [64], b2 [64], b3 [4]
-  int g;
-  __device__ float b1(int t, int j) const { return p[16 * t + 4 * g + j]; }
-  __device__ float b2(int t, int j) const { return p[64 + 16 * t + 4 * g + j]; }
-  __device__ float b3(int j) const { return g == 0 ? p[128 + j] : 0.0f; }
-};
-
-// Epoch shuffle: position i of the epoch reads sample perm(i), perm a
-// pseudo-random bijection of [0, n): a 4-round Feistel network on 2h bits
-// (2h >= log2 n, round function SplitMix64 of (key, round, half)) with
-// cycle-walking into [0, n).  Walking the cycle of a bijection returns to a
-// value below n (at worst to i itself), so the loop terminates.
-__device__ __forceinline__ uint64_t smix64(uint64_t x) {
-  x += 0x9E3779B97F4A7C15ull;
-  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-  return x ^ (x >> 31);
-}
-
-__device__ __forceinline__ uint32_t feistel_perm(uint32_t i, const MlpPerm& p) {
-  const uint32_t mask = (1u << p.h) - 1u;
-  uint32_t x = i;
-  do {
-    uint32_t L = x >> p.h, R = x & mask;
-    #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t F = (uint32_t)smix64(p.key ^ ((uint64_t)r << 40) ^ R) & mask;
-      const uint32_t t = R;
-      R = L ^ F;
-      L = t;
-    }
-    x = (L << p.h) | R;
-  } while (x >= p.n);
-  return x;
-}
-
-// LDS row strides (bf16 elements): site-major rows of 64 units, unit-major
-// rows of 32 samples; padded against bank conflicts
-constexpr int SROW = 72;
-constexpr int TROW = 40;
-
-// forward of one tile of 16 samples.  xin: B operand of layer 1 (lanes g == 0
-// hold the 4 BF16 features of sample r).  Hs1/Hs2: this wave's site-major
-// LDS tiles [16][SROW].  z1/z2 (optional) receive the pre-activations in the
-// D layout; y receives the output (lanes g == 0, outputs 0..3 of sample r).
-// sync: per-wave tiles need only the wave's own LDS order (SYNC_WAVE), the
-// training kernel's single-wave blocks use a block barrier
-enum { SYNC_BLOCK = 0, SYNC_WAVE = 1 };
-template <int SYNC>
-__device__ __forceinline__ void tile_sync() {
-  if constexpr (SYNC == SYNC_WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
-template <bool KEEP, int SYNC = SYNC_BLOCK, class Bias = RegBias>
-__device__ __forceinline__ void forward16(const Mats& w, const Bias& bias, bf16x8 xin, __bf16* Hs1, __bf16* Hs2,
-                                          int r, int g, f32x4* z1, f32x4* z2, f32x4& y) {
-  // each product starts from its bias (the accumulator's initial value), so
-  // no separate bias addition follows it
-  #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const f32x4 c = {bias.b1(t, 0), bias.b1(t, 1), bias.b1(t, 2), bias.b1(t, 3)};
-    const f32x4 d = mfma(w.w1[t], xin, c);
-    bf16x4 h;
-    #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float z = d[j];
-      if (KEEP) z1[t][j] = z;
-      h[j] = (__bf16)silu(z);
-    }
-    *(bf16x4*)(Hs1 + r * SROW + 16 * t + 4 * g) = h;
-  }
-  tile_sync<SYNC>();
-  bf16x8 b2[2];
-  #pragma unroll
-  for (int kk = 0; kk < 2; ++kk) b2[kk] = *(const bf16x8*)(Hs1 + r * SROW + 32 * kk + 8 * g);
-  #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const f32x4 c = {bias.b2(t, 0), bias.b2(t, 1), bias.b2(t, 2), bias.b2(t, 3)};
-    f32x4 d = mfma(w.w2[t][0], b2[0], c);
-    d = mfma(w.w2[t][1], b2[1], d);
-    bf16x4 h;
-    #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float z = d[j];
-      if (KEEP) z2[t][j] = z;
-      h[j] = (__bf16)silu(z);
-    }
-    *(bf16x4*)(Hs2 + r * SROW + 16 * t + 4 * g) = h;
-  }
-  tile_sync<SYNC>();
-  bf16x8 b3[2];
-  #pragma unroll
-  for (int kk = 0; kk < 2; ++kk) b3[kk] = *(const bf16x8*)(Hs2 + r * SROW + 32 * kk + 8 * g);
-  const f32x4 c = {bias.b3(0), bias.b3(1), bias.b3(2), bias.b3(3)};
-  f32x4 d = mfma(w.w3[0], b3[0], c);
-  d = mfma(w.w3[1], b3[1], d);
-  y = d;
-}
-
-// ---------------------------------------------------------------------------
-// inference
-// ---------------------------------------------------------------------------
-// Each wave takes tiles of 16 samples on its own (its LDS tiles are private,
-// so only the wave's own LDS order matters); the biases sit in LDS, shared by
-// the block, which keeps fewer registers live per lane.
-__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ params, const float* __restrict__ X,
-                                                     int64_t n, float* __restrict__ out) {
-  __shared__ __bf16 lds[4][2][16 * SROW];
-  __shared__ float sbias[132];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-  if (threadIdx.x < 132)
-    sbias[threadIdx.x] = threadIdx.x < 64    ? params[MLP_OB1 + threadIdx.x]
-                         : threadIdx.x < 128 ? params[MLP_OB2 + threadIdx.x - 64]
-                                             : params[MLP_OB3 + threadIdx.x - 128];
-  Mats w;
-  load_mats(params, r, g, w);
-  __syncthreads();
-  const LdsBias bias{sbias, g};
-  const int64_t ntiles = (n + 15) / 16;
-  const int64_t stride = (int64_t)gridDim.x * 4;
-  for (int64_t tile = blockIdx.x * 4ll + wv; tile < ntiles; tile += stride) {
-    const int64_t s = tile * 16 + r;
-    const bool live = s < n;
-    bf16x8 xin = zero8();
-    if (g == 0 && live) {
-      #pragma unroll
-      for (int k = 0; k < 4; ++k) xin[k] = (__bf16)X[s * 4 + k];
-    }
-    f32x4 y;
-    forward16<false, SYNC_WAVE>(w, bias, xin, lds[wv][0], lds[wv][1], r, g, nullptr, nullptr, y);
-    if (g == 0 && live) *(f32x4*)(out + s * 4) = y;
-    tile_sync<SYNC_WAVE>();  // the wave's LDS tiles are rewritten by its next tile
-  }
-}
-
-// The network's normalised input features of moments (rho, j1, j2, 2E):
-// (u1, u2, 2E/rho, |u|^2) with u = j / rho, each mapped by (v - shift) * scale
-// and rounded to FP32.  FP64, one reciprocal of rho per site; the training
-// pairs and the solver's network start share this function.
-__device__ __forceinline__ float4 mlp_features(const double* __restrict__ M, int64_t n, int64_t s,
-                                               const MlpNorm& nm) {
-  const double ir = 1.0 / M[s];
-  const double u1 = M[n + s] * ir, u2 = M[2 * n + s] * ir, e = M[3 * n + s] * ir;
-  const double uu = u1 * u1 + u2 * u2;
-  float4 x;
-  x.x = (float)((u1 - nm.in_shift[0]) * nm.in_scale[0]);
-  x.y = (float)((u2 - nm.in_shift[1]) * nm.in_scale[1]);
-  x.z = (float)((e - nm.in_shift[2]) * nm.in_scale[2]);
-  x.w = (float)((uu - nm.in_shift[3]) * nm.in_scale[3]);
-  return x;
-}
-
-// The solver's network start: warm[4][n] = (mu0 - ln rho, mu1, mu2, mu3) =
-// y / out_scale + out_shift for the network output y of M's features.  A wave
-// takes 64 sites per pass: every lane builds the features of one site (into
-// the wave's LDS as BF16 rows), the four 16-site tiles go through the matrix
-// cores, and every lane writes the four outputs of its site (coalesced per
-// output row).
-__global__ __launch_bounds__(256) void k_mlp_warm(const float* __restrict__ params, const double* __restrict__ M,
-                                                  MlpNorm nm, int64_t n, float* __restrict__ warm) {
-  __shared__ __bf16 lds[4][2][16 * SROW];
-  __shared__ float sbias[132];
-  __shared__ __bf16 sx[4][64 * 4];  // per wave: BF16 features of its 64 sites
-  __shared__ float sy[4][64][5];     // per wave: outputs of its 64 sites (padded rows)
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-  if (threadIdx.x < 132)
-    sbias[threadIdx.x] = threadIdx.x < 64    ? params[MLP_OB1 + threadIdx.x]
-                         : threadIdx.x < 128 ? params[MLP_OB2 + threadIdx.x - 64]
-                                             : params[MLP_OB3 + threadIdx.x - 128];
-  Mats w;
-  load_mats(params, r, g, w);
-  __syncthreads();
-  const LdsBias bias{sbias, g};
-  float oinv[4];
-  #pragma unroll
-  for (int k = 0; k < 4; ++k) oinv[k] = 1.0f / nm.out_scale[k];
-  __bf16* xs = sx[wv];
-  const int64_t ngroups = (n + 63) / 64;
-  const int64_t stride = (int64_t)gridDim.x * 4;
-  for (int64_t grp = blockIdx.x * 4ll + wv; grp < ngroups; grp += stride) {
-    const int64_t s = grp * 64 + lane;
-    const bool live = s < n;
-    float4 x = {0.f, 0.f, 0.f, 0.f};
-    if (live) x = mlp_features(M, n, s, nm);
-    bf16x4 xb;
-    xb[0] = (__bf16)x.x;
-    xb[1] = (__bf16)x.y;
-    xb[2] = (__bf16)x.z;
-    xb[3] = (__bf16)x.w;
-    *(bf16x4*)(xs + lane * 4) = xb;
-    tile_sync<SYNC_WAVE>();
-    #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      bf16x8 xin = zero8();
-      if (g == 0) {
-        const bf16x4 v = *(const bf16x4*)(xs + (16 * h + r) * 4);
-        #pragma unroll
-        for (int k = 0; k < 4; ++k) xin[k] = v[k];
-      }
-      f32x4 y;
-      forward16<false, SYNC_WAVE>(w, bias, xin, lds[wv][0], lds[wv][1], r, g, nullptr, nullptr, y);
-      if (g == 0) {
-        #pragma unroll
-        for (int k = 0; k < 4; ++k) sy[wv][16 * h + r][k] = y[k];
-      }
-      tile_sync<SYNC_WAVE>();  // the wave's LDS tiles are rewritten by its next tile
-    }
-    if (live) {
-      #pragma unroll
-      for (int k = 0; k < 4; ++k) warm[k * n + s] = sy[wv][lane][k] * oinv[k] + nm.out_shift[k];
-    }
-    tile_sync<SYNC_WAVE>();  // sy and the feature rows are rewritten by the next pass
-  }
-}
-
-// training pairs from moments M and multipliers mu ([4][n] each): the
-// network's normalised inputs X [n][4] (the features of the solver's network start,
-// the same arithmetic) and, when mu is given, its normalised targets T
-// [n][4] = ((mu0 - ln rho, mu1, mu2, mu3) - out_shift) * out_scale
-__global__ __launch_bounds__(256) void k_mlp_pairs(const double* __restrict__ M, const double* __restrict__ mu,
-                                                   MlpNorm nm, int64_t n, float* __restrict__ X,
-                                                   float* __restrict__ T) {
-  for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < n; s += (int64_t)gridDim.x * 256) {
-    *(float4*)(X + 4 * s) = mlp_features(M, n, s, nm);
-    if (T) {
-      const double tg[4] = {mu[s] - ::log(M[s]), mu[n + s], mu[2 * n + s], mu[3 * n + s]};
-      float4 t;
-      t.x = (float)((tg[0] - nm.out_shift[0]) * nm.out_scale[0]);
-      t.y = (float)((tg[1] - nm.out_shift[1]) * nm.out_scale[1]);
-      t.z = (float)((tg[2] - nm.out_shift[2]) * nm.out_scale[2]);
-      t.w = (float)((tg[3] - nm.out_shift[3]) * nm.out_scale[3]);
-      *(float4*)(T + 4 * s) = t;
-    }
-  }
-}
-
-hipError_t launch_mlp_pairs(const MlpNorm& nm, const double* M, const double* mu, int64_t n, float* X, float* T,
-                            hipStream_t s) {
-  int64_t nb = (n + 255) / 256;
-  if (nb > 8192) nb = 8192;
-  if (nb > 0) hipLaunchKernelGGL(k_mlp_pairs, dim3((unsigned)nb), dim3(256), 0, s, M, mu, nm, n, X, mu ? T : nullptr);
-  return hipGetLastError();
-}
-
-static unsigned fwd_grid(int64_t n) {
-  const int64_t tiles = (n + 15) / 16;
-  int64_t nb = (tiles + 3) / 4;
-  return (unsigned)(nb < 2048 ? (nb > 0 ? nb : 1) : 2048);
-}
-
-hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n, float* Y, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_forward, dim3(fwd_grid(n)), dim3(256), 0, s, params, X, n, Y);
-  return hipGetLastError();
-}
-
-hipError_t launch_mlp_warm(const float* params, const MlpNorm& nm, const double* M, int64_t n, float* warm,
-                           hipStream_t s) {
-  const int64_t groups = (n + 63) / 64;
-  int64_t nb = (groups + 3) / 4;
-  nb = nb < 2048 ? (nb > 0 ? nb : 1) : 2048;
-  hipLaunchKernelGGL(k_mlp_warm, dim3((unsigned)nb), dim3(256), 0, s, params, M, nm, n, warm);
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // gradient of the MSE loss L = (1/(4 n)) sum_s sum_o (y_so - t_so)^2

@@ -38,7 +38,7 @@ STEP_SOURCES = ("lbm_step.hpp", "lbm_step_f32q9.hip", "lbm_step_f64q9.hip", "lbm
 
 
 FSTAR_SOURCES = ("lbm_fstar.hip", "lbm_fstar.hpp", "lbm_fstar_dev.hpp", "lbm_fstar_site.hpp", "lbm_device.hpp",
-                 "lbm_mlp.hip")
+                 "lbm_mlp_infer.hip", "lbm_mlp_dev.hpp")
 # the solver kernels by start, and the network start
 FSTAR_KERNELS = {"plain_newton": "k_fstar<4>(", "rest": "k_fstar<0>(", "closed_form": "k_fstar<1>(", "mlp": "k_fstar<2>(",
                  "exact_start": "k_fstar<3>(", "mlp_forward": "k_mlp_warm("}
