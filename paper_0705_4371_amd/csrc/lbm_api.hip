@@ -326,6 +326,8 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   g.ny = cfg->ny;
   g.pitch = c->pitch;
   g.plane = c->plane;
+  g.inv_nx = 1.0 / (double)cfg->nx;
+  g.inv_pitch = 1.0 / (double)c->pitch;
   for (int s = 0; s < 4; ++s) g.bc[s] = cfg->bc[s];
   if (cfg->solid_w > 0 && cfg->solid_h > 0) {
     g.sx0 = cfg->solid_x0;

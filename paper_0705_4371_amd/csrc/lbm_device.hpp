@@ -63,7 +63,24 @@ struct Geom {
   int32_t kmax;                  // k
   int32_t out_qe;                // outlet quasiequilibrium: QE_POLY or QE_ENTROPIC_MM
   int32_t pad0;
+  double inv_nx, inv_pitch;      // 1 / nx, 1 / pitch (site index -> coordinates)
 };
+
+// q = floor(s / d) and r = s - q d for 0 <= s < 2^40 and 0 < d < 2^32: the
+// quotient from the FP64 reciprocal (its error, below 2^-50 s / d < 1e-5,
+// moves it by at most one) corrected by one step either way; a 64-bit
+// integer division would take a long instruction sequence per site
+__device__ __forceinline__ void divmod(int64_t s, int64_t d, double inv_d, int64_t& q, int64_t& r) {
+  q = (int64_t)((double)s * inv_d);
+  r = s - q * d;
+  if (r < 0) {
+    --q;
+    r += d;
+  } else if (r >= d) {
+    ++q;
+    r -= d;
+  }
+}
 
 // State layout: tiles of 64 sites of one row.  Population i of site (x, y)
 // lives at ((y * (pitch / 64) + x / 64) * Q + i) * 64 + x % 64, so a

@@ -18,7 +18,8 @@ __global__ __launch_bounds__(256) void k_init(StepArgs a, const double* __restri
   const Geom& g = a.g;
   const int64_t N = g.nx * g.ny;
   for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
-    const int64_t y = s / g.nx, x = s - y * g.nx;
+    int64_t x, y;
+    divmod((int64_t)s, g.nx, g.inv_nx, y, x);
     double fs[Q];
     if (is_solid(g, x, y)) {
       #pragma unroll
@@ -39,7 +40,8 @@ __global__ __launch_bounds__(256) void k_get(StepArgs a, T* __restrict__ out) {
   const Geom& g = a.g;
   const int64_t N = g.nx * g.ny;
   for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
-    const int64_t y = s / g.nx, x = s - y * g.nx;
+    int64_t x, y;
+    divmod((int64_t)s, g.nx, g.inv_nx, y, x);
     T f[Q];
     if (is_solid(g, x, y)) {
       #pragma unroll
@@ -59,7 +61,8 @@ __global__ __launch_bounds__(256) void k_set(StepArgs a, const T* __restrict__ i
   const int64_t N = g.nx * g.ny;
   bool bad = false;
   for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
-    const int64_t y = s / g.nx, x = s - y * g.nx;
+    int64_t x, y;
+    divmod((int64_t)s, g.nx, g.inv_nx, y, x);
     #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const T v = in[(int64_t)i * N + s];
@@ -77,7 +80,8 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, double* __restrict_
   const Geom& g = a.g;
   const int64_t N = g.nx * g.ny;
   for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
-    const int64_t y = s / g.nx, x = s - y * g.nx;
+    int64_t x, y;
+    divmod((int64_t)s, g.nx, g.inv_nx, y, x);
     double fd[Q];
     if (is_solid(g, x, y)) {
       #pragma unroll
@@ -107,7 +111,8 @@ __global__ __launch_bounds__(256) void k_sums(StepArgs a) {
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   // sites in layout order (a wavefront covers one 64-site tile)
   for (int64_t p = blockIdx.x * 256ll + threadIdx.x; p < g.plane; p += (int64_t)gridDim.x * 256) {
-    const int64_t y = p / g.pitch, x = p - y * g.pitch;
+    int64_t x, y;
+    divmod(p, g.pitch, g.inv_pitch, y, x);
     if (x >= g.nx || is_solid(g, x, y)) continue;
     T f[Q];
     load_site_fast<T, Q, PULL>(A, g, x, y, f);
@@ -208,7 +213,8 @@ __global__ __launch_bounds__(256) void k_init_M_moments(StepArgs a, const double
   const Geom& g = a.g;
   const int64_t N = g.nx * g.ny;
   for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
-    const int64_t y = s / g.nx, x = s - y * g.nx;
+    int64_t x, y;
+    divmod((int64_t)s, g.nx, g.inv_nx, y, x);
     const bool sol = is_solid(g, x, y);
     const double r = sol ? 1.0 : rho0[s];
     a.Mbuf[s] = r;
@@ -224,7 +230,8 @@ __global__ __launch_bounds__(256) void k_init_M_pops(StepArgs a) {
   const Geom& g = a.g;
   const int64_t N = g.nx * g.ny;
   for (int64_t s = blockIdx.x * 256ll + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
-    const int64_t y = s / g.nx, x = s - y * g.nx;
+    int64_t x, y;
+    divmod((int64_t)s, g.nx, g.inv_nx, y, x);
     double fs[9];
     if (is_solid(g, x, y)) {
       #pragma unroll

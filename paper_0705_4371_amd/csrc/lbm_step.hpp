@@ -386,7 +386,8 @@ __device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
   const T* __restrict__ A = (const T*)a.A;
   T* __restrict__ B = (T*)a.B;
   const Geom& g = a.g;
-  const int64_t y = site / g.nx, x = site - y * g.nx;
+  int64_t x, y;
+  divmod((int64_t)site, g.nx, g.inv_nx, y, x);
   T fs[Q];
   if constexpr (QE == QE_ENTROPIC_M) {
     fstar_from_state<T>(a.mu, g.nx * g.ny, site, fs);
@@ -406,7 +407,8 @@ __device__ __forceinline__ void reset_site(const StepArgs& a, uint32_t site) {
 template <typename T, int Q, int QE, bool PULL>
 __device__ __forceinline__ double rank_site(const StepArgs& a, const T* __restrict__ A, const Geom& g,
                                             uint32_t site) {
-  const int64_t y = site / g.nx, x = site - y * g.nx;
+  int64_t x, y;
+  divmod((int64_t)site, g.nx, g.inv_nx, y, x);
   T fT[Q];
   load_site_fast<T, Q, PULL>(A, g, x, y, fT);
   double fd[Q];
@@ -1126,7 +1128,8 @@ __global__ __launch_bounds__(64) void k_fstep_fallback(StepArgs s, FstarArgs a) 
     if (it < 0) atomicAdd(&S.failed, 1ull);
     else atomicMax(&S.maxres_bits, (unsigned long long)__double_as_longlong(res));
 
-    const int64_t y = i / g.nx, x = i - y * g.nx;
+    int64_t x, y;
+    divmod((int64_t)i, g.nx, g.inv_nx, y, x);
     T f[9], fs[9];
     load_site<T, 9, PULL>((const T*)s.A, g, x, y, f);
     fstar_pop<T>((T)(q.a * rho), (T)q.X, (T)q.Y, (T)q.Z, fs);
