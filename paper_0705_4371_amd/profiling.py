@@ -12,9 +12,8 @@
 - ``valu``: vector, transcendental, FP64 and matrix-core instruction counts
   of the f*_M solver and network-start kernels per 64 sites, from counter
   runs over the 4096 x 2048 moment field, as JSON (with the hash of those
-  kernels' sources).  For each kernel the dispatches are grouped by their
-  exact instruction count (the kernels are deterministic) and the largest
-  group is taken: the field's timed repetitions.
+  kernels' sources): per kernel the median over the field's dispatches
+  (those with at least half the largest vector count).
 
 Usage (from the repository root):
   python -m paper_0705_4371_amd.profiling stats DIR --command "..." --title "..."
@@ -30,6 +29,7 @@ import glob
 import hashlib
 import json
 import os
+import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -124,27 +124,32 @@ def pmc_summary(a) -> dict:
 
 
 def valu_summary(a) -> dict:
-    per = {}  # dispatch id -> (kernel name, {counter: value})
-    for d in a.dirs:
+    # dispatch (run, id) -> (kernel name, {counter: value}); the runs need
+    # not dispatch in the same order, so each counter is taken as the median
+    # over the dispatches of a kernel in the run that counted it
+    per = {}
+    for k, d in enumerate(a.dirs):
         for r in _rows(_one(os.path.join(d, "**", "*counter_collection.csv"))):
-            did = int(r["Dispatch_Id"])
-            name, cnt = per.setdefault(did, (r["Kernel_Name"], {}))
-            if name == r["Kernel_Name"]:
-                cnt[r["Counter_Name"]] = float(r["Counter_Value"])
+            name, cnt = per.setdefault((k, int(r["Dispatch_Id"])), (r["Kernel_Name"], {}))
+            cnt[r["Counter_Name"]] = float(r["Counter_Value"])
     waves = a.sites / 64.0
     out = {"workload": a.workload, "sites": a.sites, "fstar_source_hash": fstar_source_hash(),
            "unit": "instructions per wavefront of 64 sites", "commands": a.command, "kernels": {}}
     for key, match in FSTAR_KERNELS.items():
-        groups = {}
-        for did, (name, cnt) in per.items():
-            if match in name and all(c in cnt for c in VALU_COUNTERS):
-                groups.setdefault(tuple(cnt[c] for c in VALU_COUNTERS), []).append(did)
-        if not groups:
+        c, nd = {}, 0
+        for k in VALU_COUNTERS:
+            vals = [cnt[k] for name, cnt in per.values() if match in name and k in cnt]
+            if not vals:
+                break
+            # the field's dispatches (the largest), not the smaller training-pair solve
+            top = max(vals)
+            vals = [v for v in vals if v >= 0.5 * top]
+            c[k] = statistics.median(vals)
+            nd = max(nd, len(vals))
+        if len(c) != len(VALU_COUNTERS):
             continue
-        vals, ids = max(groups.items(), key=lambda kv: len(kv[1]))
-        c = dict(zip(VALU_COUNTERS, vals))
         out["kernels"][key] = {
-            "kernel": match.rstrip("("), "dispatches": len(ids),
+            "kernel": match.rstrip("("), "dispatches": nd,
             "valu": round(c["SQ_INSTS_VALU"] / waves, 1),
             "transcendental": round((c["SQ_INSTS_VALU_TRANS_F32"] + c["SQ_INSTS_VALU_TRANS_F64"]) / waves, 1),
             "fp64": round((c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"])
