@@ -157,7 +157,8 @@ __device__ __forceinline__ void fstar_from_state(const double* __restrict__ st, 
 }
 
 // block-wide exclusive offset of `flag` and one global atomic per block on
-// *counter; s_cnt: 4 words of LDS; returns the slot of a flagged lane
+// *counter; s_cnt: STEP_TX / 64 words of LDS; returns the slot of a flagged
+// lane
 __device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter, uint32_t* s_cnt,
                                                  uint32_t* s_base) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -165,7 +166,9 @@ __device__ __forceinline__ uint32_t block_append(bool flag, uint32_t* counter, u
   if (lane == 0) s_cnt[w] = (uint32_t)__popcll(mask);
   __syncthreads();
   if (tid == 0) {
-    const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    uint32_t tot = 0u;
+    #pragma unroll
+    for (int v = 0; v < STEP_TX / 64; ++v) tot += s_cnt[v];
     *s_base = tot ? atomicAdd(counter, tot) : 0u;
   }
   __syncthreads();
@@ -284,7 +287,7 @@ __device__ __forceinline__ void count_step(const StepArgs& a) {
 template <bool PULL>
 __device__ __forceinline__ void append_screened(const StepArgs& a, bool scr, uint32_t site, bool bad) {
   if (__syncthreads_or(scr)) {
-    __shared__ uint32_t s_cnt[4], s_base;
+    __shared__ uint32_t s_cnt[STEP_TX / 64], s_base;
     const uint32_t slot = block_append(scr, &a.ctr[C_SCREEN], s_cnt, &s_base);
     if (scr) a.screen[slot] = site;
   }
