@@ -49,6 +49,7 @@ def test_static_solve_matches_handle_solve():
         n = M.shape[1]
         _compare(lbm, solver, M, lbm.LBM_START_DEFAULT, label="rest")
         _compare(lbm, solver, M, lbm.LBM_START_CLOSED_FORM, label="closed form")
+        _compare(lbm, solver, M, lbm.LBM_START_PLAIN, label="plain FP64 Newton")
         _compare(lbm, solver, M, lbm.LBM_START_MLP, net=net, label="network")
         mu_prev, _, _, _ = solver.solve(M, start=lbm.LBM_START_DEFAULT)
         mu_prev = mu_prev * (1 + 1e-3 * torch.sin(torch.arange(n, device=M.device, dtype=M.dtype)))
