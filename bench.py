@@ -193,7 +193,8 @@ def cylinder_leg(args, torch, lbm, W, net):
     start and from the trained network start."""
     d, rho, u = W.CONFIGS["cylinder_2400x800_re20000_fstarM"]()
     e0 = W.iso_energy(u[0], u[1])
-    out = {"lattice": "%dx%d" % (d["nx"], d["ny"]), "steps": max(1, args.cyl_steps // 100) * min(100, max(1, args.cyl_steps))}
+    out = {"lattice": "%dx%d" % (d["nx"], d["ny"]), "steps": max(1, args.cyl_steps // 1000) * min(1000, max(1, args.cyl_steps)),
+           "sampling": "the statistics of every 1000th step"}
     for name, start in (("rest", lbm.LBM_START_DEFAULT), ("mlp", lbm.LBM_START_MLP),
                         ("previous_step", lbm.LBM_START_PREV)):
         cfg = lbm.config_from_workload(d, lbm.LBM_FP32, fstar_start=start,
@@ -204,15 +205,19 @@ def cylinder_leg(args, torch, lbm, W, net):
         t0 = time.perf_counter()
         fb = 0
         upd = 0
-        sel = 0
         above = 0
         failed = 0
         maxres = 0.0
-        chunk = min(100, max(1, args.cyl_steps))
+        chunk = min(1000, max(1, args.cyl_steps))
         nch = max(1, args.cyl_steps // chunk)
+        done, nonfinite = 0, 0
         for _ in range(nch):
             lat.step(chunk)
             st, _, _ = lat.stats()
+            if st.nonfinite:
+                nonfinite = 1
+                break
+            done += 1
             fb += st.n_fallback
             upd += st.newton_updates
             above += st.n_above_delta
@@ -220,14 +225,17 @@ def cylinder_leg(args, torch, lbm, W, net):
             maxres = max(maxres, st.max_resid)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        nch = max(done, 1)
         st, _, ds = lat.stats(sel_cap=256)
         fluid = d["nx"] * d["ny"] - d["solid"][2] * d["solid"][3]
-        out[name] = {"MLUPS": round(fluid * nch * chunk / dt / 1e6, 1),
+        out[name] = {"steps_run": int(st.step), "nonfinite": nonfinite,
+                     "MLUPS": round(fluid * nch * chunk / dt / 1e6, 1),
                      "ms_per_step": round(dt * 1e3 / (nch * chunk), 4),
                      "fallback_sites_sampled_steps": int(fb),
                      "fallback_rate": fb / (fluid * nch),
                      "newton_updates_per_site": upd / (fluid * nch),
                      "failed_sites_sampled_steps": int(failed), "max_residual_sampled_steps": maxres,
+                     "mean_n_above_delta_sampled": round(above / nch, 2),
                      "last_step": {"n_above_delta": st.n_above_delta, "n_selected": st.n_selected,
                                    "max_dS": st.max_dS, "kth_dS": st.kth_dS, "nonfinite": st.nonfinite},
                      "selected_total": st.total_selected, "mass": st.mass, "energy": st.energy}
@@ -509,7 +517,7 @@ def main():
     ap.add_argument("--no-wide", action="store_true", help="skip the wide-distribution f*_M solves")
     ap.add_argument("--no-channel", action="store_true", help="skip the 1200 x 400 cylinder channel runs")
     ap.add_argument("--channel-steps", type=int, default=50000)
-    ap.add_argument("--cyl-steps", type=int, default=2000)
+    ap.add_argument("--cyl-steps", type=int, default=50000)
     ap.add_argument("--fx", type=int, default=4096)
     ap.add_argument("--fy", type=int, default=2048)
     ap.add_argument("--pairs-log2", type=int, default=24)
