@@ -143,6 +143,27 @@ def test_cylinder_fstarM_full_size():
     lat.close()
 
 
+def test_cylinder_fstarM_50000_steps_stays_converged():
+    """The f*_M cylinder (2400 x 800, Re = 20000, k = 256) run for the 50,000
+    steps proposed for it, from the rest start: finite, every site of every
+    sampled step at the residual target with no failed site, mass kept
+    (the inlet and outlet exchange mass, within 1e-3 of the initial)."""
+    torch = torch_gpu()
+    say("f*_M cylinder 2400 x 800, 50000 steps")
+    d, rho, u = W.CONFIGS["cylinder_2400x800_re20000_fstarM"]()
+    e0 = W.iso_energy(u[0], u[1])
+    lat = lattice(d, FP32, rho, u, twoE0=e0)
+    st0, _, _ = lat.stats()
+    for c in range(10):
+        lat.step(5000)
+        st, _, _ = lat.stats()
+        say("  step", st.step, "above", st.n_above_delta, "failed", st.n_failed, "max resid", st.max_resid)
+        assert st.nonfinite == 0 and st.n_failed == 0 and st.max_resid <= 1e-10
+    assert st.step == 50000
+    assert abs(st.mass - st0.mass) <= 1e-3 * st0.mass
+    lat.close()
+
+
 def test_shear_layer_full_size_fp64():
     """The FP64 context at the full size (2.4 GB per population buffer)."""
     torch = torch_gpu()
