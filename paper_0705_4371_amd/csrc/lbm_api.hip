@@ -382,7 +382,7 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
   ALLOC(c->sel, sizeof(uint32_t) * kcap);
   ALLOC(c->sel_ds, sizeof(double) * kcap);
   ALLOC(c->st, sizeof(DevStats));
-  ALLOC(c->partials, sizeof(double) * 4 * 1024);
+  ALLOC(c->partials, sizeof(double) * 4 * SUM_BLOCKS);
   {
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {

@@ -102,7 +102,6 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, double* __restrict_
 // FP64 sums over fluid sites of rho, rho u1, rho u2, 2E of the current
 // pre-collision state (the conservation diagnostics): per-thread sums in a
 // fixed grid-stride order, per-block partials, then one block in fixed order
-constexpr int SUM_BLOCKS = 1024;
 
 template <typename T, int Q, bool PULL>
 __global__ __launch_bounds__(256) void k_sums(StepArgs a) {

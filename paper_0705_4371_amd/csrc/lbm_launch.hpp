@@ -53,6 +53,9 @@ constexpr int HIST_WORDS = HIST_BINS + HIST_COARSE;
 // workgroups of the partition kernel (one per-workgroup max / min each)
 constexpr int PART_BLOCKS = 1024;
 constexpr int STEP_TX = 256;  // sites per step-kernel block (one row segment)
+// workgroups of the conservation sums (per-workgroup FP64 partials, added in
+// fixed order): enough sites in flight to stream the state from HBM
+constexpr int SUM_BLOCKS = 8192;
 
 struct StepArgs {
   const void* A;   // state read this step
@@ -69,7 +72,7 @@ struct StepArgs {
   uint32_t* sel;
   double* sel_ds;
   DevStats* st;
-  double* partials;  // [1024][4] FP64 block partials of the conservation sums
+  double* partials;  // [SUM_BLOCKS][4] FP64 block partials of the conservation sums
   double* Mbuf;      // f*_M only: moments [4][N] of the current step
   const double* mu;  // f*_M only: multipliers [4][N] of the current step
   float thr_a, thr_b;  // FP32 screen threshold: thr_a - thr_b * sqrt(rho)
