@@ -115,3 +115,17 @@ def test_probe_and_spectrum_reject_bad_arguments_without_gpu(L):
     assert lib.lbm_dft_power(buf, 0, buf, None, None) == L.LBM_E_INVAL
     assert lib.lbm_dft_power(buf, (1 << 31) + 1, buf, None, None) == L.LBM_E_INVAL
     assert lib.lbm_set_fstar_tolerance(None, 1e-10, 2e-6, 16, 6) == L.LBM_E_INVAL
+
+
+def test_learned_start_entries_reject_bad_arguments_without_gpu(L):
+    """The network's pairs and start entries and the allocation-free solve
+    validate their arguments on the host, before any HIP call."""
+    lib = L.load()
+    buf = (C.c_double * 8)()
+    out = (C.c_float * 8)()
+    assert lib.lbm_mlp_warm_start(None, buf, 1, out, None) == L.LBM_E_INVAL
+    assert lib.lbm_mlp_warm_start(None, buf, -1, out, None) == L.LBM_E_INVAL
+    assert lib.lbm_mlp_pairs(None, buf, None, 1, out, None, None) == L.LBM_E_INVAL
+    # a start outside LBM_START_* is refused before the solve touches a device
+    assert lib.lbm_fstar_solve_static(buf, 1, buf, 7, None, 1e-10, 2e-6, 16, 6, None, None, None, None) \
+        == L.LBM_E_INVAL
