@@ -186,11 +186,14 @@ def fp64_leg(args, torch, lbm, W):
             "nonfinite": st.nonfinite}
 
 
-def cylinder_leg(args, torch, lbm, W, net):
+def cylinder_leg(args, torch, lbm, W, net, solver=None):
     """Flow past the square cylinder on 2400 x 800 at Re = 20000 with the
     entropic f*_M quasiequilibrium in every step (per-site Newton, plain-Newton
     fallback) and Ehrenfests' steps (delta = 1e-3, k = 256), from the rest
-    start and from the trained network start."""
+    start and from the trained network start.  With a solver, the solve of
+    the moments of every fluid site after the rest-start run's last step is
+    timed from each start as on the moment field (the network start's gain
+    on the cylinder's own distribution)."""
     d, rho, u = W.CONFIGS["cylinder_2400x800_re20000_fstarM"]()
     e0 = W.iso_energy(u[0], u[1])
     out = {"lattice": "%dx%d" % (d["nx"], d["ny"]), "steps": max(1, args.cyl_steps // 1000) * min(1000, max(1, args.cyl_steps)),
@@ -239,6 +242,20 @@ def cylinder_leg(args, torch, lbm, W, net):
                      "last_step": {"n_above_delta": st.n_above_delta, "n_selected": st.n_selected,
                                    "max_dS": st.max_dS, "kth_dS": st.kth_dS, "nonfinite": st.nonfinite},
                      "selected_total": st.total_selected, "mass": st.mass, "energy": st.energy}
+        if name == "rest" and solver is not None and not nonfinite:
+            import numpy as np
+            rho_t, ru_t, e2_t = lat.moments()
+            x0, y0, w, h = d["solid"]
+            solid = np.zeros((d["ny"], d["nx"]), bool)
+            solid[y0:y0 + h, x0:x0 + w] = True
+            fl = torch.from_numpy(np.flatnonzero(~solid.reshape(-1))).cuda()
+            Mc = torch.stack([rho_t.reshape(-1), ru_t[0].reshape(-1), ru_t[1].reshape(-1),
+                              e2_t.reshape(-1)]).index_select(1, fl).contiguous()
+            del rho_t, ru_t, e2_t, fl
+            out["field_solve"] = {"field": "moments of the %d fluid sites after step %d of the rest-start run"
+                                           % (Mc.shape[1], int(st.step)),
+                                  "solve": _solve_starts(torch, lbm, solver, Mc, net)}
+            del Mc
         lat.close()
         # every sampled step reached the residual target at every site
         assert failed == 0 and maxres <= 1e-10, (name, failed, maxres)
@@ -388,6 +405,19 @@ def _fstar_counts():
     return d["kernels"] if d.get("fstar_source_hash") == fstar_source_hash() else None
 
 
+def _update_hist(it, st):
+    """Newton updates per site (the solver's histogram of the first pass) and
+    the largest count of each wavefront (64 consecutive sites), which sets
+    the wavefront's time, as {updates: number of sites / wavefronts}."""
+    import numpy as np
+    per_site = {str(j) if j < 15 else "15+": int(c) for j, c in enumerate(st.iter_hist) if c}
+    u = it.cpu().numpy()
+    nw = u.size // 64
+    wmax = np.bincount(u[:nw * 64].reshape(nw, 64).max(axis=1))
+    return {"updates_per_site_hist": per_site,
+            "updates_per_wave_max_hist": {str(j): int(c) for j, c in enumerate(wmax) if c}}
+
+
 def _solve_starts(torch, lbm, solver, M, net, counts=None):
     """Times the f*_M solve of the field M from the rest, closed-form and
     network starts, the network start's forward alone, and the solve from
@@ -409,12 +439,13 @@ def _solve_starts(torch, lbm, solver, M, net, counts=None):
                         ("closed_form", lbm.LBM_START_CLOSED_FORM), ("mlp", lbm.LBM_START_MLP)):
         kw = dict(start=start, net=net if start == lbm.LBM_START_MLP else None, mu=mu, iters=it, status=stt)
         _, _, _, st = solver.solve(M, stats=True, **kw)          # statistics (synchronising)
+        hist = _update_hist(it, st)
         ms = _time_gpu(torch, lambda: solver.solve(M, stats=False, **kw))
         res[name] = {"ms": round(ms, 4), "Msites_per_s": round(n / ms / 1e3, 1),
                      "mean_newton_updates": round(st.mean_fp32_iters + st.mean_fp64_iters, 4),
                      "mean_fp32": round(st.mean_fp32_iters, 4), "mean_fp64": round(st.mean_fp64_iters, 4),
                      "fallback": int(st.n_fallback), "failed": int(st.n_failed),
-                     "max_residual": st.max_resid}
+                     "max_residual": st.max_resid, **hist}
     warm = torch.empty((4, n), dtype=torch.float32, device="cuda")
     res["mlp"]["forward_ms"] = round(_time_gpu(torch, lambda: net.warm_start(M, out=warm)), 4)
     # exact start: the converged multipliers as the previous-state start
@@ -474,7 +505,7 @@ def fstar_leg(args, torch, lbm, W):
     out["solve"] = _solve_starts(torch, lbm, solver, M, net, counts=_fstar_counts())
     del M
     if not args.no_cylinder:
-        out["cylinder_fstarM"] = cylinder_leg(args, torch, lbm, W, net)
+        out["cylinder_fstarM"] = cylinder_leg(args, torch, lbm, W, net, solver)
     out["speedup_mlp_vs_plain_newton"] = out["solve"]["speedup_mlp_vs_plain_newton"]
     out["speedup_mlp_vs_rest"] = out["solve"]["speedup_mlp_vs_rest"]
     out["speedup_closed_form_vs_rest"] = out["solve"]["speedup_closed_form_vs_rest"]
