@@ -341,7 +341,7 @@ __device__ __forceinline__ double elbm_alpha(const double* f, const double* fs) 
 // leading 1/3 and enters the bracket multiplied by |s (1 + s)| < 0.07; 14
 // terms for |s| <= 1/4; the logarithm beyond.
 template <int Q>
-__device__ __forceinline__ double dS_fp64(const double* f, const double* fs) {
+__device__ __forceinline__ double dS_fp64_site(const double* f, const double* fs) {
   double acc = 0.0;
   for (int i = 0; i < Q; ++i) {
     const double a = f[i], b = fs[i];
@@ -380,6 +380,68 @@ __device__ __forceinline__ double dS_fp64(const double* f, const double* fs) {
     }
   }
   return acc;
+}
+
+// the G series of one population (the bracket sg t (1 + s (1 + s) G(t))),
+// cut after t^6 (|s| <= 1/16) or t^13 (|s| <= 1/4), as above
+template <bool LONG>
+__device__ __forceinline__ double dS_series(double sg, double s) {
+  const double t = s * s;
+  double G;
+  if constexpr (LONG) {
+    G = 1.0 / 29.0;
+    G = G * t + 1.0 / 27.0;
+    G = G * t + 1.0 / 25.0;
+    G = G * t + 1.0 / 23.0;
+    G = G * t + 1.0 / 21.0;
+    G = G * t + 1.0 / 19.0;
+    G = G * t + 1.0 / 17.0;
+    G = G * t + 1.0 / 15.0;
+  } else {
+    G = 1.0 / 15.0;
+  }
+  G = G * t + 1.0 / 13.0;
+  G = G * t + 1.0 / 11.0;
+  G = G * t + 1.0 / 9.0;
+  G = G * t + 1.0 / 7.0;
+  G = G * t + 1.0 / 5.0;
+  G = G * t + 1.0 / 3.0;
+  return sg * t * (1.0 + s * (1.0 + s) * G);
+}
+
+// The same Delta S with the order of the series chosen per population for
+// the whole wavefront: when every active lane's s lies within 1/16 (or 1/4)
+// the wavefront evaluates the short (or long) series, each accurate to
+// round-off wherever it is used, as one straight-line sequence instead of
+// every branch that some lane needs; otherwise each lane takes its own form
+// as above.  +inf for f < 0 or f* <= 0, as above.
+template <int Q>
+__device__ __forceinline__ double dS_fp64(const double* f, const double* fs) {
+  double acc = 0.0;
+  bool bad = false;
+  #pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double a = f[i], b = fs[i];
+    const double sg = a + b, s = (a - b) * rcp64(sg);
+    const double as = __builtin_fabs(s);
+    const bool pos = a > 0.0 && b > 0.0;  // false for a NaN
+    if (__all(pos && as <= 0.0625)) {
+      acc += dS_series<false>(sg, s);
+    } else if (__all(pos && as <= 0.25)) {
+      acc += dS_series<true>(sg, s);
+    } else if (!(a >= 0.0) || !(b > 0.0)) {
+      bad = true;
+    } else if (a == 0.0) {
+      acc += b;
+    } else if (as <= 0.0625) {
+      acc += dS_series<false>(sg, s);
+    } else if (as <= 0.25) {
+      acc += dS_series<true>(sg, s);
+    } else {
+      acc += a * ::log(a / b) - a + b;
+    }
+  }
+  return bad ? __builtin_inf() : acc;
 }
 
 }  // namespace lbm
