@@ -70,7 +70,7 @@ def _oracle_rate(oracle, cfg, f, steps, omp):
 
 def cpu_baseline(args, net_params=None):
     """The oracle (FP64 C) timed on this host: the plain single-threaded
-    build (the parity judge) and the same source built with OpenMP over its
+    build (the parity reference) and the same source built with OpenMP over its
     site loops, on bounded samples of the workloads (see `sample`)."""
     import numpy as np
     import oracle

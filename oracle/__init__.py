@@ -35,7 +35,7 @@ MLP_NPARAM = 4740
 
 def build(force: bool = True, omp: bool = False) -> str:
     """Compile oracle.c with gcc into liboracle.so (plain -O2, no fast-math,
-    single-threaded: the judge); with omp=True into liboracle_omp.so with
+    single-threaded: the parity reference); with omp=True into liboracle_omp.so with
     OpenMP over the site loops (the same arithmetic per site; used only to
     time the oracle on all host cores)."""
     out = _LIB_OMP if omp else _LIB
