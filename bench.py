@@ -439,13 +439,12 @@ def _solve_starts(torch, lbm, solver, M, net, counts=None):
                         ("closed_form", lbm.LBM_START_CLOSED_FORM), ("mlp", lbm.LBM_START_MLP)):
         kw = dict(start=start, net=net if start == lbm.LBM_START_MLP else None, mu=mu, iters=it, status=stt)
         _, _, _, st = solver.solve(M, stats=True, **kw)          # statistics (synchronising)
-        hist = _update_hist(it, st)
         ms = _time_gpu(torch, lambda: solver.solve(M, stats=False, **kw))
         res[name] = {"ms": round(ms, 4), "Msites_per_s": round(n / ms / 1e3, 1),
                      "mean_newton_updates": round(st.mean_fp32_iters + st.mean_fp64_iters, 4),
                      "mean_fp32": round(st.mean_fp32_iters, 4), "mean_fp64": round(st.mean_fp64_iters, 4),
                      "fallback": int(st.n_fallback), "failed": int(st.n_failed),
-                     "max_residual": st.max_resid, **hist}
+                     "max_residual": st.max_resid}
     warm = torch.empty((4, n), dtype=torch.float32, device="cuda")
     res["mlp"]["forward_ms"] = round(_time_gpu(torch, lambda: net.warm_start(M, out=warm)), 4)
     # exact start: the converged multipliers as the previous-state start
@@ -456,6 +455,13 @@ def _solve_starts(torch, lbm, solver, M, net, counts=None):
     res["exact_start"] = {"ms": round(ms, 4), "mean_fp32": round(st.mean_fp32_iters, 4),
                           "mean_fp64": round(st.mean_fp64_iters, 4), "failed": int(st.n_failed),
                           "max_residual": st.max_resid}
+    # update histograms, after every timing (their host work would let the
+    # clocks drop before the next timed solve)
+    for name, start in (("plain_newton", lbm.LBM_START_PLAIN), ("rest", lbm.LBM_START_DEFAULT),
+                        ("closed_form", lbm.LBM_START_CLOSED_FORM), ("mlp", lbm.LBM_START_MLP)):
+        _, _, _, st = solver.solve(M, stats=True, start=start, net=net if start == lbm.LBM_START_MLP else None,
+                                   mu=mu, iters=it, status=stt)
+        res[name].update(_update_hist(it, st))
     # HBM floor of each solve: M read (32 B/site), mu written (32 B), the
     # update count and status bytes (2 B), and the network start read back
     # (16 B), or the previous multipliers (32 B) for the exact start; the
