@@ -135,7 +135,8 @@ def valu_summary(a) -> dict:
     waves = a.sites / 64.0
     out = {"workload": a.workload, "sites": a.sites, "fstar_source_hash": fstar_source_hash(),
            "unit": "instructions per wavefront of 64 sites", "commands": a.command, "kernels": {}}
-    for key, match in FSTAR_KERNELS.items():
+    kernels = dict(kv.split("=", 1) for kv in a.kernel) if a.kernel else FSTAR_KERNELS
+    for key, match in kernels.items():
         c, nd = {}, 0
         for k in VALU_COUNTERS:
             vals = [cnt[k] for name, cnt in per.values() if match in name and k in cnt]
@@ -155,6 +156,12 @@ def valu_summary(a) -> dict:
             "fp64": round((c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"])
                           / waves, 1),
             "mfma": round(c["SQ_INSTS_MFMA"] / waves, 1)}
+        # HBM counters, when a run counted them: raw KiB per dispatch (median)
+        for k in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = [cnt[k] for name, cnt in per.values() if match in name and k in cnt]
+            if vals:
+                top = max(vals)
+                out["kernels"][key][k.lower() + "_kib"] = round(statistics.median([v for v in vals if v >= 0.5 * top]), 1)
     return out
 
 
@@ -185,6 +192,8 @@ def main(argv=None) -> None:
     v.add_argument("--workload", default="f*_M moment field 4096x2048 (rho in [0.5, 1.5], |u| <= 0.1, "
                                           "2E/rho within 5% of isothermal), residual <= 1e-10")
     v.add_argument("--command", action="append", required=True)
+    v.add_argument("--kernel", action="append", default=[],
+                   help="KEY=SUBSTRING of a dispatch name (repeatable; default: the solver and network kernels)")
     a = ap.parse_args(argv)
     if a.what == "valu":
         json.dump(valu_summary(a), sys.stdout, indent=1)
