@@ -134,6 +134,7 @@ def valu_summary(a) -> dict:
             cnt[r["Counter_Name"]] = float(r["Counter_Value"])
     waves = a.sites / 64.0
     out = {"workload": a.workload, "sites": a.sites, "fstar_source_hash": fstar_source_hash(),
+           "step_source_hash": kernel_source_hash(),
            "unit": "instructions per wavefront of 64 sites", "commands": a.command, "kernels": {}}
     kernels = dict(kv.split("=", 1) for kv in a.kernel) if a.kernel else FSTAR_KERNELS
     for key, match in kernels.items():
