@@ -340,50 +340,9 @@ __device__ __forceinline__ double elbm_alpha(const double* f, const double* fs) 
 // t^6: the first term dropped, t^7 / 17 <= 2^-56 / 17, is < 1e-17 of G's
 // leading 1/3 and enters the bracket multiplied by |s (1 + s)| < 0.07; 14
 // terms for |s| <= 1/4; the logarithm beyond.
-template <int Q>
-__device__ __forceinline__ double dS_fp64_site(const double* f, const double* fs) {
-  double acc = 0.0;
-  for (int i = 0; i < Q; ++i) {
-    const double a = f[i], b = fs[i];
-    if (!(a >= 0.0) || !(b > 0.0)) return __builtin_inf();
-    if (a == 0.0) { acc += b; continue; }
-    const double sg = a + b, s = (a - b) * rcp64(sg);
-    const double t = s * s;
-    if (__builtin_fabs(s) <= 0.0625) {
-      double G = 1.0 / 15.0;
-      G = G * t + 1.0 / 13.0;
-      G = G * t + 1.0 / 11.0;
-      G = G * t + 1.0 / 9.0;
-      G = G * t + 1.0 / 7.0;
-      G = G * t + 1.0 / 5.0;
-      G = G * t + 1.0 / 3.0;
-      acc += sg * t * (1.0 + s * (1.0 + s) * G);
-    } else if (__builtin_fabs(s) <= 0.25) {
-      double G = 1.0 / 29.0;
-      // Horner for G(t) = sum_{j=0}^{13} t^j / (2j + 3); t <= 1/16
-      G = G * t + 1.0 / 27.0;
-      G = G * t + 1.0 / 25.0;
-      G = G * t + 1.0 / 23.0;
-      G = G * t + 1.0 / 21.0;
-      G = G * t + 1.0 / 19.0;
-      G = G * t + 1.0 / 17.0;
-      G = G * t + 1.0 / 15.0;
-      G = G * t + 1.0 / 13.0;
-      G = G * t + 1.0 / 11.0;
-      G = G * t + 1.0 / 9.0;
-      G = G * t + 1.0 / 7.0;
-      G = G * t + 1.0 / 5.0;
-      G = G * t + 1.0 / 3.0;
-      acc += sg * t * (1.0 + s * (1.0 + s) * G);
-    } else {
-      acc += a * ::log(a / b) - a + b;
-    }
-  }
-  return acc;
-}
-
-// the G series of one population (the bracket sg t (1 + s (1 + s) G(t))),
-// cut after t^6 (|s| <= 1/16) or t^13 (|s| <= 1/4), as above
+//
+// The bracket sg t (1 + s (1 + s) G(t)) of one population, with G cut after
+// t^6 (short) or t^13 (long):
 template <bool LONG>
 __device__ __forceinline__ double dS_series(double sg, double s) {
   const double t = s * s;
@@ -409,12 +368,12 @@ __device__ __forceinline__ double dS_series(double sg, double s) {
   return sg * t * (1.0 + s * (1.0 + s) * G);
 }
 
-// The same Delta S with the order of the series chosen per population for
-// the whole wavefront: when every active lane's s lies within 1/16 (or 1/4)
-// the wavefront evaluates the short (or long) series, each accurate to
+// Delta S of one site.  The order of the series is chosen per population
+// for the whole wavefront: when every active lane's s lies within 1/16 (or
+// 1/4) the wavefront evaluates the short (or long) series, each accurate to
 // round-off wherever it is used, as one straight-line sequence instead of
 // every branch that some lane needs; otherwise each lane takes its own form
-// as above.  +inf for f < 0 or f* <= 0, as above.
+// (series by its own |s|, or the logarithm).
 template <int Q>
 __device__ __forceinline__ double dS_fp64(const double* f, const double* fs) {
   double acc = 0.0;
