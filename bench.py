@@ -111,8 +111,11 @@ def cpu_baseline(args, net_params=None):
     mc = 480000 * args.cpu_channel_steps / dtc / 1e6
     out["channel_1200x400"] = {"steps": args.cpu_channel_steps, "seconds": round(dtc, 3), "MLUPS": round(mc, 3),
                                "cores": threads, "extrapolated_50k_steps_s": round(50000 * 480000 / (mc * 1e6), 1)}
-    # f*_M of a sample of the 4096 x 2048 moment field to residual 1e-10
-    M = W.moment_field()[:, ::(1 << 23) // args.cpu_fstar_sites][:, :args.cpu_fstar_sites].copy()
+    # f*_M of the 4096 x 2048 moment field to residual 1e-10 (the whole
+    # field from the rest and closed-form starts; the network start, whose
+    # forward pass the oracle runs on one thread, on an evenly spaced sample)
+    Mf = W.moment_field()
+    M = Mf[:, ::max(1, Mf.shape[1] // args.cpu_fstar_sites)][:, :args.cpu_fstar_sites].copy()
     ns = M.shape[1]
     fst = {"sites": ns, "cores": threads, "residual": 1e-10}
     for name, start in (("rest", 0), ("closed_form", 1)):
@@ -120,9 +123,13 @@ def cpu_baseline(args, net_params=None):
         _, it, bad = oracle.fstar_field(M, 1e-10, start, omp=True)
         dtf = time.perf_counter() - t0
         fst[name] = {"Msites_per_s": round(ns / dtf / 1e6, 3), "mean_newton_updates": round(float(it.mean()), 3),
-                     "unconverged": bad}
+                     "unconverged": bad, "seconds": round(dtf, 2)}
+    del Mf
     if net_params is not None:
         # the network start in FP64 (forward pass on the oracle), then Newton
+        M = M[:, ::max(1, ns // args.cpu_mlp_sites)][:, :args.cpu_mlp_sites].copy()
+        ns = M.shape[1]
+        fst["mlp_sites"] = ns
         nm = np.concatenate(W.mlp_norm()).astype(np.float32)
         t0 = time.perf_counter()
         y = oracle.mlp_forward(net_params.astype(np.float64), oracle.mlp_features(M, nm))
@@ -132,7 +139,7 @@ def cpu_baseline(args, net_params=None):
         dtf = time.perf_counter() - t0
         fst["mlp"] = {"Msites_per_s": round(ns / dtf / 1e6, 3), "mean_newton_updates": round(float(it.mean()), 3),
                       "unconverged": bad, "note": "FP64 forward pass of the trained network on one thread"}
-    out["fstar_4096x2048_sample"] = fst
+    out["fstar_4096x2048"] = fst
     return out
 
 
@@ -545,7 +552,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--cpu-channel-steps", type=int, default=20)
-    ap.add_argument("--cpu-fstar-sites", type=int, default=1 << 16)
+    ap.add_argument("--cpu-fstar-sites", type=int, default=1 << 23, help="sites of the CPU f*_M solves (the whole field)")
+    ap.add_argument("--cpu-mlp-sites", type=int, default=1 << 16, help="sites of the CPU network-start solve")
     ap.add_argument("--no-fstar", action="store_true", help="skip the f*_M / MLP leg")
     ap.add_argument("--no-active", action="store_true", help="skip the leg with many sites above delta")
     ap.add_argument("--active-rows", type=int, default=256)
