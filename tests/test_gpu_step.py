@@ -102,6 +102,29 @@ def test_delta_zero_all_sites_candidates():
     assert out[0][2].n_above_delta == 130 * 20
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_delta_s_series_orders_mixed_in_a_wavefront(prec):
+    """The FP64 Delta S of a population is its short series (|s| <= 1/16), its
+    long series (|s| <= 1/4) or the logarithm, and a wavefront evaluates one
+    series for all its lanes only when every lane allows it.  Perturbation
+    amplitudes cycling through 0.02, 0.3 and 0.9 along x put lanes that need
+    each form into every wavefront (64 consecutive sites); with delta = 0
+    every site is a candidate and its Delta S is held to the oracle's."""
+    torch = torch_gpu()
+    d, rho, u = W.shear_layer(nx=192, ny=8, k=64, delta=0.0, width=5.0)
+    say("case mixed series orders prec", prec)
+    lat = lattice(d, prec, rho, u)
+    f0 = lat.get_populations().double().cpu().numpy()
+    r = np.random.default_rng(17)
+    amp = np.array([0.02, 0.3, 0.9])[np.arange(d["nx"]) % 3]
+    f0 = f0 * (1 + amp[None, None, :] * r.uniform(-1, 1, f0.shape))
+    lat.set_populations(torch.from_numpy(f0))
+    f = lat.get_populations().double().cpu().numpy()
+    g, o, st = compare_step(lat, d, f, TOL[prec], label="mixed series orders")
+    assert st.n_above_delta == d["nx"] * d["ny"]
+    lat.close()
+
+
 def test_invalid_sites_rank_first():
     torch = torch_gpu()
     d, rho, u = W.shear_layer(nx=128, ny=16, k=6, delta=1e-5, width=5.0)
