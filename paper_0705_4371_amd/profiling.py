@@ -147,7 +147,8 @@ def valu_summary(a) -> dict:
             top = max(vals)
             vals = [v for v in vals if v >= 0.5 * top]
             c[k] = statistics.median(vals)
-            nd = max(nd, len(vals))
+            if k == "SQ_INSTS_VALU":  # the dispatches counted (a zero counter selects them all)
+                nd = len(vals)
         if len(c) != len(VALU_COUNTERS):
             continue
         out["kernels"][key] = {

@@ -88,3 +88,31 @@ def test_bench_reports_traffic_only_for_the_current_kernel(tmp_path, monkeypatch
     with open(path, "w") as fh:
         json.dump({"kernel_source_hash": "0" * 16, "hbm_bytes_per_launch": 123}, fh)
     assert bench.traffic_from_profile("wl", "fp32", 1) is None          # kernel changed since
+
+
+def test_valu_summary_per_wavefront_with_kernel_patterns(tmp_path):
+    """Instruction counts per 64 sites: the median over a kernel's dispatches
+    with at least half its largest count (the smaller dispatches are another
+    workload), counters split over two runs, named kernel patterns, and the
+    HBM counters in KiB when a run counted them."""
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    vals = {"SQ_INSTS_VALU": 1000.0, "SQ_INSTS_VALU_TRANS_F32": 40.0, "SQ_INSTS_VALU_TRANS_F64": 10.0,
+            "SQ_INSTS_MFMA": 0.0}
+    rows1 = []
+    for d, scale in ((1, 1.0), (2, 1.02), (3, 0.98), (4, 0.1)):     # dispatch 4: a smaller solve
+        rows1 += [[d, "void k_x<0>(A)", c, v * scale] for c, v in vals.items()]
+    rows2 = []
+    for d in (1, 2, 3):
+        rows2 += [[d, "void k_x<0>(A)", "SQ_INSTS_VALU_FMA_F64", 200.0], [d, "void k_x<0>(A)", "SQ_INSTS_VALU_ADD_F64", 64.0],
+                  [d, "void k_x<0>(A)", "SQ_INSTS_VALU_MUL_F64", 56.0], [d, "void k_x<0>(A)", "FETCH_SIZE", 512.0]]
+    _write_csv(str(tmp_path / "r1" / "p_counter_collection.csv"), hdr, rows1)
+    _write_csv(str(tmp_path / "r2" / "p_counter_collection.csv"), hdr, rows2)
+    a = types.SimpleNamespace(dirs=[str(tmp_path / "r1"), str(tmp_path / "r2")], sites=640, workload="w",
+                              command=["c"], kernel=["x=k_x<0>("])
+    out = profiling.valu_summary(a)
+    k = out["kernels"]["x"]
+    assert k["dispatches"] == 3
+    assert k["valu"] == 100.0 and k["transcendental"] == 5.0 and k["fp64"] == 32.0 and k["mfma"] == 0.0
+    assert k["fetch_size_kib"] == 512.0 and "write_size_kib" not in k
+    assert out["fstar_source_hash"] == profiling.fstar_source_hash()
+    assert out["step_source_hash"] == profiling.kernel_source_hash()
