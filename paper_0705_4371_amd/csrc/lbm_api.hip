@@ -420,6 +420,13 @@ int lbm_init(const lbm_config* cfg, const double* rho0, const double* u0, const 
                : cfg->fstar_start == LBM_START_MLP        ? START_WARM
                : cfg->fstar_start == LBM_START_PREV       ? START_PREV
                                                           : START_REST;
+    // the fused step's grid: the workgroups the device holds at once
+    a.fgrid[0] = a.fgrid[1] = 0;
+    if (c->fkind != START_WARM) {
+      const bool elbm = cfg->collision == LBM_COLL_ELBM;
+      a.fgrid[0] = fstep_resident(cfg->precision, c->fkind, false, elbm);
+      a.fgrid[1] = fstep_resident(cfg->precision, c->fkind, true, elbm);
+    }
     a.Mbuf = c->Mbuf;
     a.mu = c->mubuf;
   }

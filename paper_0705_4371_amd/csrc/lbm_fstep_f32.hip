@@ -9,4 +9,6 @@ hipError_t launch_fstep_f32(const StepArgs& a, const FstarArgs& fa, int start, b
   return pull ? fstep_p<float, true>(a, fa, start, s, ev0, ev1) : fstep_p<float, false>(a, fa, start, s, ev0, ev1);
 }
 
+int fstep_resident_f32(int start, bool pull, bool elbm) { return fstep_resident_p<float>(start, pull, elbm); }
+
 }  // namespace lbm

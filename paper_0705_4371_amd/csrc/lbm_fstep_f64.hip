@@ -9,4 +9,6 @@ hipError_t launch_fstep_f64(const StepArgs& a, const FstarArgs& fa, int start, b
   return pull ? fstep_p<double, true>(a, fa, start, s, ev0, ev1) : fstep_p<double, false>(a, fa, start, s, ev0, ev1);
 }
 
+int fstep_resident_f64(int start, bool pull, bool elbm) { return fstep_resident_p<double>(start, pull, elbm); }
+
 }  // namespace lbm

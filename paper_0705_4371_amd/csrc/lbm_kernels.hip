@@ -337,6 +337,10 @@ hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s) {
   return hipGetLastError();
 }
 
+int fstep_resident(int prec, int start, bool pull, bool elbm) {
+  return prec == 1 ? fstep_resident_f64(start, pull, elbm) : fstep_resident_f32(start, pull, elbm);
+}
+
 hipError_t launch_fstep(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s, hipEvent_t ev0,
                         hipEvent_t ev1) {
   hipError_t e = launch_fstar_clear(fa, s);

@@ -80,6 +80,9 @@ struct StepArgs {
   int prec, Q, qe;
   int coll;  // 0 LBGK, 1 ELBM
   int one_wg;  // ranking and selection by one workgroup (k_select_one)
+  // f*_M time step: workgroups of k_fstep for the canonical [0] and pulled
+  // [1] layouts, the number the device holds at once (0: FSTAR_MAX_BLOCKS)
+  int fgrid[2];
   // monitoring point: site index (-1: none), ring [3][probe_cap] of
   // (rho, u1, u2) of f(x, t), and the device count of recorded samples
   int64_t probe;
@@ -104,6 +107,9 @@ hipError_t launch_moments_M(const StepArgs& a, bool pull, hipStream_t s);
 // sites, then ranking and selection
 hipError_t launch_fstep(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s, hipEvent_t ev0,
                         hipEvent_t ev1);
+// workgroups of the f*_M step kernel of this precision, start, layout and
+// collision that the device holds at once (occupancy x compute units), or 0
+int fstep_resident(int prec, int start, bool pull, bool elbm);
 // f*_M initial state: moments of the initial fields into a.Mbuf, and (after
 // the solve) f = f*(mu) into the state buffer a.B
 hipError_t launch_init_M_moments(const StepArgs& a, const double* rho0, const double* u0, const double* twoE0,

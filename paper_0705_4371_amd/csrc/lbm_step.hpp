@@ -1189,9 +1189,11 @@ static hipError_t step_q(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t
 template <typename T, bool PULL, bool ELBM>
 static hipError_t fstep_t(const StepArgs& a, const FstarArgs& fa, int start, hipStream_t s, hipEvent_t ev0,
                           hipEvent_t ev1) {
-  // capped grid, a multiple of 8 (the XCD remap), so that the statistics
-  // atomics stay few
-  const unsigned gr = (unsigned)(a.nblocks < FSTAR_MAX_BLOCKS ? a.nblocks : FSTAR_MAX_BLOCKS);
+  // a grid-stride loop over the row segments by the workgroups the device
+  // holds at once (one round, no partly filled last round; the statistics
+  // atomics stay few), else by at most FSTAR_MAX_BLOCKS
+  const int64_t cap = a.fgrid[PULL ? 1 : 0] > 0 ? a.fgrid[PULL ? 1 : 0] : FSTAR_MAX_BLOCKS;
+  const unsigned gr = (unsigned)(a.nblocks < cap ? a.nblocks : cap);
   if (ev0) { hipError_t e = hipEventRecord(ev0, s); if (e != hipSuccess) return e; }
   if (start == START_CLOSED) hipLaunchKernelGGL((k_fstep<T, PULL, START_CLOSED, ELBM>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
   else if (start == START_PREV) hipLaunchKernelGGL((k_fstep<T, PULL, START_PREV, ELBM>), dim3(gr), dim3(STEP_TX), 0, s, a, fa);
@@ -1200,6 +1202,32 @@ static hipError_t fstep_t(const StepArgs& a, const FstarArgs& fa, int start, hip
   hipLaunchKernelGGL((k_fstep_fallback<T, PULL, ELBM>), dim3(64), dim3(64), 0, s, a, fa);
   select_t<T, 9, QE_ENTROPIC_M, PULL>(a, s);
   return hipGetLastError();
+}
+
+// workgroups of k_fstep<T, PULL, START, ELBM> resident at once on the
+// current device: its occupancy per compute unit times the compute units
+template <typename T, bool PULL, int START, bool ELBM>
+static int fstep_resident_t() {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_fstep<T, PULL, START, ELBM>),
+                                                   STEP_TX, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu > 0 && cus > 0 ? per_cu * cus : 0;
+}
+
+template <typename T, bool PULL, bool ELBM>
+static int fstep_resident_s(int start) {
+  if (start == START_CLOSED) return fstep_resident_t<T, PULL, START_CLOSED, ELBM>();
+  if (start == START_PREV) return fstep_resident_t<T, PULL, START_PREV, ELBM>();
+  return fstep_resident_t<T, PULL, START_REST, ELBM>();
+}
+
+template <typename T>
+static int fstep_resident_p(int start, bool pull, bool elbm) {
+  if (pull) return elbm ? fstep_resident_s<T, true, true>(start) : fstep_resident_s<T, true, false>(start);
+  return elbm ? fstep_resident_s<T, false, true>(start) : fstep_resident_s<T, false, false>(start);
 }
 
 template <typename T, bool PULL>
@@ -1216,6 +1244,8 @@ hipError_t launch_step_f64q9(const StepArgs& a, bool pull, hipStream_t s, hipEve
 hipError_t launch_step_f64q3(const StepArgs& a, bool pull, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_fstep_f32(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s,
                            hipEvent_t ev0, hipEvent_t ev1);
+int fstep_resident_f32(int start, bool pull, bool elbm);
+int fstep_resident_f64(int start, bool pull, bool elbm);
 hipError_t launch_fstep_f64(const StepArgs& a, const FstarArgs& fa, int start, bool pull, hipStream_t s,
                            hipEvent_t ev0, hipEvent_t ev1);
 
